@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the even-odd Wilson-clover hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch: the 12 spin-colour
+point sources on a 32^3x64 lattice with chemical potential mu = 0.1
+(U = exp(0.2 i H), kappa = 0.124, c_SW = 1.5) solved to a true relative
+residual of 1e-10 through the odd-site Schur system: source preparation, the
+fused 12-column CG with FP32 (or FP16) inner iterations and FP64 reliable
+updates, reconstruction and FP64 residual checks.  Gauge field, clover and
+sources are resident in HBM before the timed region.
+
+value = algorithmic HBM bytes the library accounts for the K timed solves
+(every kernel's inputs read once, outputs written once) / wall time, GB/s.
+The JSON line also carries the roofline of the EO-clover Dslash kernel
+K1 = T_ee^-1 D_eo (HIP events on the kernel's stream), the FP64-CG vs mixed
+time-to-solution on the same GPU, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "EO-clover Dslash GB/s (%HBM peak); mixed vs FP64 CG time-to-1e-10; p99 latency"
+HBM_PEAK_GBS = 8000.0
+PREC_NAMES = {"f64": 0, "f32": 1, "f16": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--dims", default="32,32,32,64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU decomposition is described in DESIGN.md but not built.", flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_1711_03836_amd import bqhip as bq
+    from paper_1711_03836_amd import inputs
+
+    dims = tuple(int(v) for v in args.dims.split(","))
+    kappa, csw, mu, eps, tol = 0.124, 1.5, 0.1, 0.2, 1e-10
+    inner = PREC_NAMES[args.inner]
+    V = int(np.prod(dims))
+
+    log(f"[bench] generating U = exp(i*{eps}*H) on {dims} ...")
+    t0 = time.time()
+    U = inputs.gauge_field(dims, eps, seed=20171110)
+    b = inputs.point_sources(dims)
+    log(f"[bench] inputs ready in {time.time() - t0:.1f}s")
+
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, t_bc=-1)
+    op = bq.Op(G, kappa, csw, mu)
+    nrhs = b.shape[0]
+    fb = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, nrhs)
+    fx = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, nrhs)
+    fb.put(b)
+    plaq = G.plaquette()
+    log(f"[bench] plaquette {plaq:.6f}; autotuning stencil for {args.inner} x {nrhs} and f64 x {nrhs}")
+    for prec in {inner, 0}:
+        op.autotune(prec, nrhs)
+        log(f"[bench]   tune prec={prec}: recon/R/bs = {ctx.tune_get(prec, nrhs)}")
+
+    def solve(prec):
+        rc, info = op.solve(fb, fx, tol, system=bq.BQ_SYS_M, inner_prec=prec, chunk=args.chunk,
+                            use_graph=bool(args.graph))
+        return info, op.stats()
+
+    for i in range(args.warmup):
+        info, st = solve(inner)
+        log(f"[bench] warmup {i}: {st['seconds']*1e3:.1f} ms, iters {info[0]['iters']}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_bytes = 0.0
+    infos = []
+    for i in range(args.steps):
+        info, st = solve(inner)
+        tot_bytes += st["bytes"]
+        infos.append((info, st))
+        log(f"[bench] step {i}: {st['seconds']*1e3:.1f} ms device, {st['bytes']/1e9:.1f} GB, "
+            f"iters {max(c['iters'] for c in info)}, reliable {max(c['reliable_updates'] for c in info)}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = tot_bytes / wall / 1e9
+    last_info, last_st = infos[-1]
+    assert all(c["converged"] for c in last_info), last_info
+    worst_true = max(c["true_rel_resid"] for c in last_info)
+    worst_full = max(c["full_rel_resid"] for c in last_info)
+
+    # FP64 CG on the same GPU, same sources, same tolerance
+    mixed_vs = None
+    if not args.no_fp64:
+        info64, st64 = solve(0)
+        assert all(c["converged"] for c in info64), info64
+        mixed_vs = {
+            "fp64_ms": st64["seconds"] * 1e3, "mixed_ms": last_st["seconds"] * 1e3,
+            "speedup": st64["seconds"] / last_st["seconds"],
+            "fp64_iters": max(c["iters"] for c in info64), "mixed_iters": max(c["iters"] for c in last_info),
+            "mixed_reliable_updates": max(c["reliable_updates"] for c in last_info),
+            "fp64_gbs": st64["bytes"] / st64["seconds"] / 1e9,
+            "true_rel_resid_fp64": max(c["true_rel_resid"] for c in info64),
+            "true_rel_resid_mixed": worst_true, "full_rel_resid_mixed": worst_full,
+            "inner_prec": args.inner,
+        }
+        log(f"[bench] FP64 CG {mixed_vs['fp64_ms']:.1f} ms vs mixed {mixed_vs['mixed_ms']:.1f} ms "
+            f"(x{mixed_vs['speedup']:.2f})")
+
+    # roofline of the EO-clover Dslash K1 = T_ee^-1 D_eo, HIP events on the stream it runs on
+    dslash = {}
+    roof = None
+    stream = torch.cuda.Stream()
+    for name, prec in (("f64", 0), (args.inner, inner)):
+        fo = bq.Field(ctx, dims, bq.BQ_ODD, prec, nrhs)
+        fe = bq.Field(ctx, dims, bq.BQ_EVEN, prec, nrhs)
+        fo.put(inputs.gaussian_spinor(dims, nrhs, seed=5))
+        ms, by = op.time_apply(bq.BQ_OP_K1, fo, fe, reps=args.kernel_reps, stream=stream)
+        ms2, by2 = op.time_apply(bq.BQ_OP_MHATDAG_MHAT, fo, bq.Field(ctx, dims, bq.BQ_ODD, prec, nrhs),
+                                 reps=max(5, args.kernel_reps // 4), stream=stream)
+        dslash[name] = {"k1_ms": ms, "k1_bytes": by, "k1_gbs": by / ms / 1e6, "k1_frac": by / ms / 1e6 / HBM_PEAK_GBS,
+                        "mdagm_ms": ms2, "mdagm_gbs": by2 / ms2 / 1e6, "tune": ctx.tune_get(prec, nrhs)}
+        log(f"[bench] K1 {name} x{nrhs}: {ms:.3f} ms, {by/ms/1e6:.0f} GB/s; Mhat^dag Mhat {by2/ms2/1e6:.0f} GB/s")
+    k = dslash[args.inner]
+    roof = {"bound": "hbm", "achieved": k["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": k["k1_gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "kernel": f"K1 = T_ee^-1 D_eo, {args.inner}, {nrhs} columns, recon/R/bs={k['tune']}",
+            "bytes_per_launch": k["k1_bytes"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(dims, U, kappa, csw, mu, b, op, inner)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"{args.inner}+f64", "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} EO-clover CG on Mhat^dag Mhat, {nrhs} point sources, "
+                               f"mu={mu}, kappa={kappa}, c_SW={csw}, U=exp({eps} i H), tol {tol:g}, "
+                               f"{args.inner} inner + f64 reliable updates",
+                   "lattice": list(dims), "nrhs": nrhs, "plaquette": plaq},
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "dslash": dslash,
+        "solve": {"true_rel_resid": worst_true, "full_rel_resid": worst_full,
+                  "iters": max(c["iters"] for c in last_info),
+                  "reliable_updates": max(c["reliable_updates"] for c in last_info),
+                  "device_ms": last_st["seconds"] * 1e3, "launches": last_st["launches"],
+                  "bytes_per_solve": last_st["bytes"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(dims, U, kappa, csw, mu, b, op, inner):
+    """The CPU oracle on a bounded sample of the same workload: two CG iterations on Mhat^dag Mhat for one
+    point source on the full lattice, scaled to GB/s with the same algorithmic byte count as the GPU."""
+    from oracle import oracle as orc
+    log("[bench] CPU oracle: building clover field and inverse ...")
+    t0 = time.time()
+    ref = orc.Operator(dims, U, kappa, csw, mu=mu)
+    bp = ref.Mhat(ref.prepare(b[0]), dagger=True)
+    log(f"[bench] CPU oracle setup {time.time() - t0:.1f}s; timing 2 CG iterations")
+    iters = 2
+    t0 = time.perf_counter()
+    ref.cg(bp, 1, 1e-30, iters)
+    dt = time.perf_counter() - t0
+    Vh = int(np.prod(dims)) // 2
+    # FP64 algorithmic bytes of one CG iteration on one column: 4 stencil launches (links 8x18 + clover 72 reals
+    # per output site) + spinor traffic + vector updates, the same model the GPU library uses
+    s64 = 24 * 8
+    per_iter = 4 * Vh * (8 * 18 * 8 + 72 * 8) + Vh * (2 + 3 + 2 + 4) * s64 + Vh * 5 * s64
+    return {"value": iters * per_iter / dt / 1e9, "unit": "GB/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{iters} FP64 CG iterations on Mhat^dag Mhat, 1 of the 12 point sources, full "
+                      f"{'x'.join(map(str, dims))} lattice ({dt:.1f}s)",
+            "seconds_per_iteration": dt / iters}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * bqhip.h -- C ABI of the MI355X (gfx950) library for the hot path of BQCD's
+ * Hybrid Monte Carlo (arXiv:1711.03836): the even-odd preconditioned
+ * Wilson-clover fermion matrix with chemical potential and the conjugate
+ * gradient solve of M^dag M x = b built on it.
+ *
+ * Operator (Eq. 1 and Eq. 2 of the section on fermion actions):
+ *   (M psi)(x) = T(x) psi(x) - kappa (D psi)(x)
+ *   (D psi)(x) = sum_mu [ f+_mu(x) U_mu(x)(1 - gamma_mu) psi(x+mu)
+ *                       + f-_mu(x) U_mu(x-mu)^dag (1 + gamma_mu) psi(x-mu) ]
+ *   with f+-_{x,y,z} = 1, f+_t = e^{+mu}, f-_t = e^{-mu}, times t_bc on hops
+ *   that cross the time boundary;
+ *   T(x) = 1 + kappa c_SW sum_{mu<nu} sigma_{mu nu} (-i F_{mu nu}(x)),
+ *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu], F = (Q - Q^dag)/8 from the
+ *   four-leaf clover, made traceless; Euclidean chiral basis
+ *   (gamma_5 = diag(1,1,-1,-1)), so T is two Hermitian 6x6 blocks per site.
+ * Checkerboard storage (the volume/2 arrays of the section on SIMD
+ * vectorization): even sites have x1+x2+x3+x4 even.  The Schur system lives
+ * on odd sites:  Mhat = T_oo - kappa^2 D_oe T_ee^-1 D_eo.
+ * Solver: cg from the solver list of the section on algorithms (Tables 1-2
+ * time this solver), with FP32/FP16 inner iterations and FP64 reliable
+ * updates as options.
+ *
+ * Conventions of this ABI
+ *   - Every function returns an int: BQ_OK (0) or a negative BQ_ERR_* code;
+ *     bq_last_error() returns a thread-local message for the last failure.
+ *     No C++ exception crosses the ABI.
+ *   - Canonical host layout (C order, complex128 = two doubles re, im):
+ *       site index  i = x1 + L1*(x2 + L2*(x3 + L3*x4)), directions 0..3 = x,y,z,t
+ *       links       U[mu][i][a][b]             4*V*9 complex
+ *       spinors     psi[rhs][i][spin][colour]  nrhs*V*12 complex
+ *     A pointer flagged `on_device` is a device pointer (e.g. a torch tensor's
+ *     data_ptr) in the same canonical layout; otherwise it is host memory.
+ *   - Handles (context, gauge, op, field) are owned by the library until their
+ *     *_free / *_destroy call; freeing NULL is a no-op.  Fields hold data in the
+ *     library's own device layout (site-tiled checkerboards); bq_field_put /
+ *     bq_field_get convert from / to the canonical layout.
+ *   - `stream` is a hipStream_t or NULL.  Work is ordered after earlier work on
+ *     that stream; NULL selects the context's own stream.  bq_apply is
+ *     asynchronous on that stream; every other call returns when its results
+ *     are complete.
+ *   - All lattice extents must be even and >= 2.
+ *   - A context is not thread-safe: one host thread per context at a time.
+ */
+#ifndef BQHIP_H
+#define BQHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BQ_OK 0
+#define BQ_ERR_INVALID (-1)         /* bad argument: NULL, odd or < 2 extent, nrhs < 1, tol <= 0, mismatch */
+#define BQ_ERR_OOM (-2)             /* HBM budget exceeded or device allocation failed */
+#define BQ_ERR_NOT_CONVERGED (-3)   /* maxiter reached; x holds the last iterate, info is filled */
+#define BQ_ERR_NONFINITE (-4)       /* NaN/Inf met in the source or during the solve */
+#define BQ_ERR_CLOVER_NOT_HPD (-5)  /* a clover block is not positive definite (kappa c_SW too large) */
+#define BQ_ERR_BUSY (-6)            /* freeing a gauge field that live operators still use */
+#define BQ_ERR_DEVICE (-7)          /* a HIP runtime call failed */
+#define BQ_ERR_UNSUPPORTED (-8)     /* valid request this build does not provide */
+
+enum { BQ_F64 = 0, BQ_F32 = 1, BQ_F16 = 2 };            /* storage precision of a field / inner solve */
+enum { BQ_EVEN = 0, BQ_ODD = 1, BQ_FULL = 2 };          /* sites a field holds */
+
+/* Operator kinds for bq_apply (in -> out subsets in brackets). */
+enum {
+    BQ_OP_M = 0,              /* M = T - kappa D                         [FULL -> FULL]  */
+    BQ_OP_MDAG = 1,           /* M^dag                                   [FULL -> FULL]  */
+    BQ_OP_MHAT = 2,           /* T_oo - kappa^2 D_oe T_ee^-1 D_eo        [ODD  -> ODD]   */
+    BQ_OP_MHATDAG = 3,        /* Mhat^dag                                [ODD  -> ODD]   */
+    BQ_OP_MHATDAG_MHAT = 4,   /* Mhat^dag Mhat                           [ODD  -> ODD]   */
+    BQ_OP_DEO = 5,            /* D restricted to even rows, odd columns  [ODD  -> EVEN]  */
+    BQ_OP_DOE = 6,            /* D, odd rows, even columns               [EVEN -> ODD]   */
+    BQ_OP_DEO_DAG = 7,        /* (D^dag)_eo                              [ODD  -> EVEN]  */
+    BQ_OP_DOE_DAG = 8,        /* (D^dag)_oe                              [EVEN -> ODD]   */
+    BQ_OP_K1 = 9,             /* T_ee^-1 D_eo (the fused EO-clover Dslash) [ODD -> EVEN] */
+    BQ_OP_K1_DAG = 10,        /* T_ee^-1 (D^dag)_eo                      [ODD  -> EVEN]  */
+    BQ_OP_CLOVER = 11,        /* T                                       [FULL -> FULL]  */
+    BQ_OP_CLOVER_INV = 12,    /* T_ee^-1                                 [EVEN -> EVEN]  */
+    BQ_OP_MDAGM = 13          /* M^dag M                                 [FULL -> FULL]  */
+};
+
+/* Linear systems for bq_solve. */
+enum {
+    BQ_SYS_NORMAL = 0,        /* Mhat^dag Mhat x = b on odd sites (b, x: ODD fields)                 */
+    BQ_SYS_M = 1,             /* M x = b on the full lattice through the odd-site Schur system:
+                                 bhat = b_o + kappa D_oe T_ee^-1 b_e, CG on Mhat^dag Mhat x_o = Mhat^dag bhat,
+                                 x_e = T_ee^-1 (b_e + kappa D_eo x_o)           (b, x: FULL fields) */
+    BQ_SYS_FULL_NORMAL = 2    /* M^dag M x = b on the full lattice, no preconditioning (FULL fields) */
+};
+
+typedef struct bq_context_s* bq_context;
+typedef struct bq_gauge_s* bq_gauge;
+typedef struct bq_op_s* bq_op;
+typedef struct bq_field_s* bq_field;
+
+typedef struct {
+    double tol;        /* stop when the FP64 true residual |b' - A x| <= tol |b'| (A, b' of the CG system) */
+    int maxiter;       /* bound on inner CG iterations per right-hand side */
+    int inner_prec;    /* BQ_F64, BQ_F32 or BQ_F16 arithmetic/storage of the inner iterations */
+    double delta;      /* reliable update when |r_inner| < delta * max|r| since the last update (0: 0.1) */
+    int system;        /* BQ_SYS_* */
+    int chunk;         /* iterations between host convergence checks (0: default 16) */
+    int use_graph;     /* 1: capture a chunk of iterations in a hipGraph and replay it */
+} bq_solve_params;
+
+typedef struct {
+    int iters;              /* inner CG iterations */
+    int reliable_updates;   /* FP64 true-residual recomputations */
+    double true_rel_resid;  /* |b' - A x| / |b'|, recomputed in FP64 after the solve */
+    double full_rel_resid;  /* BQ_SYS_M: |b - M x| / |b|; otherwise equal to true_rel_resid */
+    int converged;          /* 1 if true_rel_resid <= tol */
+    int status;             /* BQ_OK or the per-column error code */
+} bq_solve_info;
+
+/* Accounting of the last bq_solve / bq_trace on an operator. */
+typedef struct {
+    double bytes;        /* algorithmic HBM bytes: every kernel's inputs read once and outputs written once
+                            (links and clover once per launch, spinors once per active right-hand side) */
+    double seconds;      /* device time of the call, HIP events on the solve stream */
+    long long launches;  /* kernel launches (kernels inside graph replays included) */
+    int chunks;          /* host convergence checks */
+    int iterations;      /* lockstep inner iterations executed for the batch */
+} bq_solve_stats;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int bq_version(void);
+
+/* Thread-local description of the last error, or "" (never NULL). */
+const char* bq_last_error(void);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory the context may hold (0 = 90% of the device's free memory); every
+ * allocation above it fails with BQ_ERR_OOM.  The context owns a HIP stream. */
+int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_context* out);
+int bq_context_destroy(bq_context ctx);
+/* Bytes of device memory the context currently holds. */
+int bq_context_hbm_used(bq_context ctx, uint64_t* used);
+
+/* Upload gauge links U[mu][i][3][3] (canonical layout above) for a lattice with
+ * extents dims[4] and time boundary sign t_bc (-1 antiperiodic, +1 periodic).
+ * The library keeps FP64, FP32 and FP16 copies (full and two-row forms).
+ * Links are used as given; the two-row form assumes SU(3). */
+int bq_gauge_upload(bq_context ctx, const int dims[4], const double* links, int links_on_device, int t_bc,
+                    bq_gauge* out);
+/* Average plaquette: mean over sites and the 6 planes of Re tr U_{mu nu}(x) / 3. */
+int bq_gauge_plaquette(bq_gauge g, double* plaq);
+/* BQ_ERR_BUSY while operators built on g are alive. */
+int bq_gauge_free(bq_gauge g);
+
+/* Build the operator M(U; kappa, c_SW, mu): clover field T on both parities and
+ * T_ee^-1, in FP64 with FP32/FP16 copies.  BQ_ERR_CLOVER_NOT_HPD if a clover
+ * block is not positive definite. */
+int bq_op_create(bq_gauge g, double kappa, double csw, double mu, bq_op* out);
+int bq_op_free(bq_op op);
+
+/* A device field of nrhs right-hand sides on `subset` sites in precision prec. */
+int bq_field_create(bq_context ctx, const int dims[4], int subset, int prec, int nrhs, bq_field* out);
+int bq_field_free(bq_field f);
+/* Copy nrhs canonical spinors (nrhs*V*12 complex, full lattice) into the field,
+ * converting to its precision; only sites of the field's subset are read. */
+int bq_field_put(bq_field f, const double* src, int src_on_device, void* stream);
+/* Copy the field out to nrhs canonical spinors; only sites of the field's
+ * subset are written, other sites of dst are left untouched. */
+int bq_field_get(bq_field f, double* dst, int dst_on_device, void* stream);
+
+/* out = Op in for Op = BQ_OP_*; in and out must have the subsets listed above,
+ * the same precision and the same nrhs.  Asynchronous on `stream`. */
+int bq_apply(bq_op op, int kind, bq_field in, bq_field out, void* stream);
+
+/* Solve the system params->system for all nrhs columns of b at once (one fused
+ * multi-RHS launch per operator step); x receives the solutions (FP64 fields).
+ * info points to nrhs entries (may be NULL).  Returns BQ_ERR_NOT_CONVERGED if
+ * some column did not reach tol within maxiter (x then holds the last iterate). */
+int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq_solve_info* info, void* stream);
+
+/* Stochastic traces Tr(M^-1) and Tr(M^-2) with nnoise complex Z2 noise vectors
+ * eta_n (components (+-1 +- i)/sqrt(2) from SplitMix64 used as a counter-based
+ * generator with seed `seed`: component (n, i, spin s, colour c) uses output
+ * k = (n*V + i)*12 + 3s + c; bit 63 gives the real sign, bit 62 the imaginary),
+ * solved `block` at a time with params (system forced to BQ_SYS_M).
+ * t1[2n], t1[2n+1] = Re, Im of eta_n^dag M^-1 eta_n; t2 likewise for M^-2.
+ * info: nnoise entries for the first solve and nnoise for the second (may be NULL). */
+int bq_trace(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_params* params, double* t1, double* t2,
+             bq_solve_info* info);
+
+/* Statistics of the last bq_solve or bq_trace call on op. */
+int bq_solve_stats_get(bq_op op, bq_solve_stats* out);
+
+/* Time `reps` back-to-back launches of one operator kind on fields in/out with
+ * HIP events recorded on the stream the kernels run on; *ms = mean per launch,
+ * *bytes = algorithmic bytes one launch must move (each input read once). */
+int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void* stream, double* ms, double* bytes);
+
+/* Kernel configuration used for a given precision and column count (filled in
+ * by the autotuner on first use, or set explicitly).  recon: 12 or 18 reals per
+ * link; R: columns per thread; bs: threads per block. */
+int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs);
+int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs);
+/* Time the candidate configurations for (op's lattice, prec, nrhs) on op and keep the fastest. */
+int bq_autotune(bq_op op, int prec, int nrhs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BQHIP_H */

@@ -1,0 +1,296 @@
+"""ctypes binding of the C ABI in include/bqhip.h (argument marshalling only).
+
+Every function of the header is exposed under the same name; non-zero return
+codes raise BqError with the library's message.  Small classes (Context,
+Gauge, Op, Field) own the handles and convert numpy arrays (host) or torch
+tensors (device) in the canonical layout:
+
+  links  (4, V, 3, 3) complex128      spinors (nrhs, V, 4, 3) complex128
+
+torch is imported before the library is loaded so that both share one HIP
+runtime in the process.  There is no fallback: without the built library
+this module raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # share torch's HIP runtime when torch is present (device buffers, streams)
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the environment
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbqhip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1711_03836_amd/build.py` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = C.CDLL(LIB_PATH)
+
+BQ_OK = 0
+ERRORS = {-1: "BQ_ERR_INVALID", -2: "BQ_ERR_OOM", -3: "BQ_ERR_NOT_CONVERGED", -4: "BQ_ERR_NONFINITE",
+          -5: "BQ_ERR_CLOVER_NOT_HPD", -6: "BQ_ERR_BUSY", -7: "BQ_ERR_DEVICE", -8: "BQ_ERR_UNSUPPORTED"}
+BQ_ERR_INVALID, BQ_ERR_OOM, BQ_ERR_NOT_CONVERGED, BQ_ERR_NONFINITE = -1, -2, -3, -4
+BQ_ERR_CLOVER_NOT_HPD, BQ_ERR_BUSY, BQ_ERR_DEVICE, BQ_ERR_UNSUPPORTED = -5, -6, -7, -8
+
+BQ_F64, BQ_F32, BQ_F16 = 0, 1, 2
+BQ_EVEN, BQ_ODD, BQ_FULL = 0, 1, 2
+(BQ_OP_M, BQ_OP_MDAG, BQ_OP_MHAT, BQ_OP_MHATDAG, BQ_OP_MHATDAG_MHAT, BQ_OP_DEO, BQ_OP_DOE, BQ_OP_DEO_DAG,
+ BQ_OP_DOE_DAG, BQ_OP_K1, BQ_OP_K1_DAG, BQ_OP_CLOVER, BQ_OP_CLOVER_INV, BQ_OP_MDAGM) = range(14)
+BQ_SYS_NORMAL, BQ_SYS_M, BQ_SYS_FULL_NORMAL = 0, 1, 2
+
+OP_SUBSETS = {BQ_OP_M: (BQ_FULL, BQ_FULL), BQ_OP_MDAG: (BQ_FULL, BQ_FULL), BQ_OP_MDAGM: (BQ_FULL, BQ_FULL),
+              BQ_OP_CLOVER: (BQ_FULL, BQ_FULL), BQ_OP_MHAT: (BQ_ODD, BQ_ODD), BQ_OP_MHATDAG: (BQ_ODD, BQ_ODD),
+              BQ_OP_MHATDAG_MHAT: (BQ_ODD, BQ_ODD), BQ_OP_DEO: (BQ_ODD, BQ_EVEN), BQ_OP_DEO_DAG: (BQ_ODD, BQ_EVEN),
+              BQ_OP_K1: (BQ_ODD, BQ_EVEN), BQ_OP_K1_DAG: (BQ_ODD, BQ_EVEN), BQ_OP_DOE: (BQ_EVEN, BQ_ODD),
+              BQ_OP_DOE_DAG: (BQ_EVEN, BQ_ODD), BQ_OP_CLOVER_INV: (BQ_EVEN, BQ_EVEN)}
+
+
+class bq_solve_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("inner_prec", C.c_int), ("delta", C.c_double),
+                ("system", C.c_int), ("chunk", C.c_int), ("use_graph", C.c_int)]
+
+
+class bq_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("true_rel_resid", C.c_double),
+                ("full_rel_resid", C.c_double), ("converged", C.c_int), ("status", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class bq_solve_stats(C.Structure):
+    _fields_ = [("bytes", C.c_double), ("seconds", C.c_double), ("launches", C.c_longlong), ("chunks", C.c_int),
+                ("iterations", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_h = C.c_void_p
+_P = C.POINTER
+_sig = {
+    "bq_version": (C.c_int, []),
+    "bq_last_error": (C.c_char_p, []),
+    "bq_context_create": (C.c_int, [C.c_int, C.c_uint64, _P(_h)]),
+    "bq_context_destroy": (C.c_int, [_h]),
+    "bq_context_hbm_used": (C.c_int, [_h, _P(C.c_uint64)]),
+    "bq_gauge_upload": (C.c_int, [_h, _P(C.c_int), C.c_void_p, C.c_int, C.c_int, _P(_h)]),
+    "bq_gauge_plaquette": (C.c_int, [_h, _P(C.c_double)]),
+    "bq_gauge_free": (C.c_int, [_h]),
+    "bq_op_create": (C.c_int, [_h, C.c_double, C.c_double, C.c_double, _P(_h)]),
+    "bq_op_free": (C.c_int, [_h]),
+    "bq_field_create": (C.c_int, [_h, _P(C.c_int), C.c_int, C.c_int, C.c_int, _P(_h)]),
+    "bq_field_free": (C.c_int, [_h]),
+    "bq_field_put": (C.c_int, [_h, C.c_void_p, C.c_int, C.c_void_p]),
+    "bq_field_get": (C.c_int, [_h, C.c_void_p, C.c_int, C.c_void_p]),
+    "bq_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_void_p]),
+    "bq_solve": (C.c_int, [_h, _h, _h, _P(bq_solve_params), _P(bq_solve_info), C.c_void_p]),
+    "bq_trace": (C.c_int, [_h, C.c_uint64, C.c_int, C.c_int, _P(bq_solve_params), _P(C.c_double), _P(C.c_double),
+                           _P(bq_solve_info)]),
+    "bq_solve_stats_get": (C.c_int, [_h, _P(bq_solve_stats)]),
+    "bq_time_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_int, C.c_void_p, _P(C.c_double), _P(C.c_double)]),
+    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
+    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+EXPORTED = tuple(_sig)
+
+
+def check(rc):
+    if rc != BQ_OK:
+        raise BqError(rc, _lib.bq_last_error().decode())
+    return rc
+
+
+def _dims(dims):
+    return (C.c_int * 4)(*[int(d) for d in dims])
+
+
+def _ptr_of(a):
+    """(pointer, on_device) for a numpy array or a torch tensor."""
+    if torch is not None and isinstance(a, torch.Tensor):
+        return C.c_void_p(a.data_ptr()), int(a.is_cuda)
+    return a.ctypes.data_as(C.c_void_p), 0
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if torch is not None and isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+# ---------------------------------------------------------------------------
+# owning wrappers
+# ---------------------------------------------------------------------------
+
+class Context:
+    def __init__(self, device=0, hbm_budget=0):
+        h = _h()
+        check(bq_context_create(int(device), int(hbm_budget), C.byref(h)))
+        self.h = h
+
+    def hbm_used(self):
+        v = C.c_uint64()
+        check(bq_context_hbm_used(self.h, C.byref(v)))
+        return v.value
+
+    def tune_get(self, prec, nrhs):
+        r, R, bs = C.c_int(), C.c_int(), C.c_int()
+        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs)))
+        return r.value, R.value, bs.value
+
+    def tune_set(self, prec, nrhs, recon, R, bs):
+        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs))
+
+    def close(self):
+        if self.h:
+            check(bq_context_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Gauge:
+    def __init__(self, ctx: Context, dims, links, t_bc=-1):
+        self.ctx, self.dims = ctx, tuple(int(d) for d in dims)
+        if not (torch is not None and isinstance(links, torch.Tensor)):
+            links = np.ascontiguousarray(links, dtype=np.complex128)
+        p, dev = _ptr_of(links)
+        h = _h()
+        check(bq_gauge_upload(ctx.h, _dims(dims), p, dev, int(t_bc), C.byref(h)))
+        self.h = h
+
+    def plaquette(self):
+        v = C.c_double()
+        check(bq_gauge_plaquette(self.h, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if self.h:
+            check(bq_gauge_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Op:
+    def __init__(self, gauge: Gauge, kappa, csw, mu=0.0):
+        self.gauge, self.ctx, self.dims = gauge, gauge.ctx, gauge.dims
+        self.kappa, self.csw, self.mu = float(kappa), float(csw), float(mu)
+        h = _h()
+        check(bq_op_create(gauge.h, self.kappa, self.csw, self.mu, C.byref(h)))
+        self.h = h
+
+    def apply(self, kind, fin, fout, stream=None):
+        check(bq_apply(self.h, kind, fin.h, fout.h, _stream(stream)))
+
+    def time_apply(self, kind, fin, fout, reps=20, stream=None):
+        ms, by = C.c_double(), C.c_double()
+        check(bq_time_apply(self.h, kind, fin.h, fout.h, int(reps), _stream(stream), C.byref(ms), C.byref(by)))
+        return ms.value, by.value
+
+    def solve(self, b, x, tol, system=BQ_SYS_NORMAL, inner_prec=BQ_F64, maxiter=100000, delta=0.1, chunk=16,
+              use_graph=False, stream=None, raise_on_error=True):
+        prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), float(delta), int(system), int(chunk),
+                              int(bool(use_graph)))
+        info = (bq_solve_info * b.nrhs)()
+        rc = bq_solve(self.h, b.h, x.h, C.byref(prm), info, _stream(stream))
+        if raise_on_error and rc != BQ_OK:
+            check(rc)
+        return rc, [i.as_dict() for i in info]
+
+    def trace(self, seed, nnoise, block, tol, inner_prec=BQ_F32, maxiter=100000, chunk=16, use_graph=False):
+        prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), 0.1, BQ_SYS_M, int(chunk),
+                              int(bool(use_graph)))
+        t1 = (C.c_double * (2 * nnoise))()
+        t2 = (C.c_double * (2 * nnoise))()
+        info = (bq_solve_info * (2 * nnoise))()
+        check(bq_trace(self.h, C.c_uint64(seed & (2**64 - 1)), int(nnoise), int(block), C.byref(prm), t1, t2, info))
+        a1 = np.frombuffer(t1, dtype=np.float64).copy()
+        a2 = np.frombuffer(t2, dtype=np.float64).copy()
+        return a1[0::2] + 1j * a1[1::2], a2[0::2] + 1j * a2[1::2], [i.as_dict() for i in info]
+
+    def stats(self):
+        st = bq_solve_stats()
+        check(bq_solve_stats_get(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def autotune(self, prec, nrhs):
+        check(bq_autotune(self.h, prec, nrhs))
+
+    def close(self):
+        if self.h:
+            check(bq_op_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Field:
+    def __init__(self, ctx: Context, dims, subset=BQ_FULL, prec=BQ_F64, nrhs=1):
+        self.ctx, self.dims = ctx, tuple(int(d) for d in dims)
+        self.subset, self.prec, self.nrhs = subset, prec, nrhs
+        self.V = int(np.prod(self.dims))
+        h = _h()
+        check(bq_field_create(ctx.h, _dims(dims), subset, prec, nrhs, C.byref(h)))
+        self.h = h
+
+    def put(self, a, stream=None):
+        """a: (nrhs, V, 4, 3) complex128 numpy array or torch tensor (host or device)."""
+        if not (torch is not None and isinstance(a, torch.Tensor)):
+            a = np.ascontiguousarray(a, dtype=np.complex128)
+        if tuple(a.shape) != (self.nrhs, self.V, 4, 3):
+            raise ValueError(f"expected shape {(self.nrhs, self.V, 4, 3)}, got {tuple(a.shape)}")
+        p, dev = _ptr_of(a)
+        check(bq_field_put(self.h, p, dev, _stream(stream)))
+
+    def get(self, out=None, stream=None):
+        """Return (nrhs, V, 4, 3) complex128; sites outside the field's subset are zero (or kept from `out`)."""
+        if out is None:
+            out = np.zeros((self.nrhs, self.V, 4, 3), dtype=np.complex128)
+        p, dev = _ptr_of(out)
+        check(bq_field_get(self.h, p, dev, _stream(stream)))
+        return out
+
+    def close(self):
+        if self.h:
+            check(bq_field_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

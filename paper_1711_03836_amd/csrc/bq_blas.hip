@@ -1,0 +1,563 @@
+// Layout conversion, BLAS-1 updates, deterministic FP64 reductions and the
+// per-column CG finalisation kernels.
+//
+// Reductions: every kernel that reduces writes one FP64 partial per wavefront
+// of 64 consecutive sites (a butterfly inside the wave), and a finalisation
+// kernel sums a column's partials in a fixed order in one workgroup.  The
+// partials depend only on which 64 sites a wave covers, so a column's result
+// is the same bit for bit whatever the block size, column tile or batch it
+// was computed in.
+#include "bq_kernels.h"
+
+namespace bq {
+namespace {
+
+template <class P>
+__host__ __device__ SpinorPtr<P> sp(const FieldArg& f)
+{
+    return SpinorPtr<P>{(typename P::unit*)f.d, f.s, f.cstride, f.sstride};
+}
+
+__device__ __forceinline__ int lex_of(const Geom& g, int parity, int j)
+{
+    const Site s = site_of(g, parity, j);
+    return s.x + g.L[0] * (s.y + g.L[1] * (s.z + g.L[2] * s.t));
+}
+
+// --------------------------------------------------------------------------
+// layout conversion between the canonical lexicographic complex128 arrays and
+// the site-tiled checkerboard storage
+// --------------------------------------------------------------------------
+
+template <class P, int NC>
+__global__ void k_links_import(const double2* __restrict__ canon, const Geom g, int parity, typename P::unit* d0,
+                               typename P::unit* d1, typename P::unit* d2, typename P::unit* d3)
+{
+    using T = typename P::real;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.Vh) return;
+    const size_t V = 2 * (size_t)g.Vh;
+    const int lex = lex_of(g, parity, j);
+    typename P::unit* dst[4] = {d0, d1, d2, d3};
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        cx<T> u[NC];
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const double2 t = canon[((size_t)mu * V + lex) * 9 + k];
+            u[k] = {(T)t.x, (T)t.y};
+        }
+        CxIO<P, NC>::store(dst[mu], j, u);
+    }
+}
+
+template <class P>
+__global__ void k_spinor_import(const double2* __restrict__ canon, const Geom g, int parity, SpinorPtr<P> f)
+{
+    using T = typename P::real;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= g.Vh) return;
+    const size_t V = 2 * (size_t)g.Vh;
+    const int lex = lex_of(g, parity, j);
+    cx<T> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const double2 t = canon[((size_t)c * V + lex) * 12 + k];
+        v[k] = {(T)t.x, (T)t.y};
+    }
+    store_spinor(f, c, j, v);
+}
+
+template <class P>
+__global__ void k_spinor_export(SpinorPtr<P> f, const Geom g, int parity, double2* __restrict__ canon)
+{
+    using T = typename P::real;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= g.Vh) return;
+    const size_t V = 2 * (size_t)g.Vh;
+    const int lex = lex_of(g, parity, j);
+    cx<T> v[12];
+    load_spinor(f, c, j, v);
+#pragma unroll
+    for (int k = 0; k < 12; k++) canon[((size_t)c * V + lex) * 12 + k] = make_double2((double)v[k].re, (double)v[k].im);
+}
+
+// --------------------------------------------------------------------------
+// BLAS-1 over n sites (a parity half, or both halves of a full field)
+// --------------------------------------------------------------------------
+
+template <class PS, class PD>
+__global__ void k_convert(SpinorPtr<PS> src, SpinorPtr<PD> dst, int n, const int* status, int statmask)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= n || !col_selected(status, statmask, c)) return;
+    cx<typename PS::real> a[12];
+    cx<typename PD::real> b[12];
+    load_spinor(src, c, j, a);
+#pragma unroll
+    for (int k = 0; k < 12; k++) b[k] = {(typename PD::real)a[k].re, (typename PD::real)a[k].im};
+    store_spinor(dst, c, j, b);
+}
+
+template <class P>
+__global__ void k_zero(SpinorPtr<P> x, int n, const int* status, int statmask)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= n || !col_selected(status, statmask, c)) return;
+    cx<typename P::real> z[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) z[k] = {0, 0};
+    store_spinor(x, c, j, z);
+}
+
+template <class P>
+__global__ void k_norm2(SpinorPtr<P> x, int n, double* partial, int nwaves)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    double s = 0.0;
+    if (j < n) {
+        cx<typename P::real> v[12];
+        load_spinor(x, c, j, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) s += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+    }
+    s = wave_sum(s);
+    const int w = j >> kTileLog;
+    if ((threadIdx.x & 63) == 0 && w < nwaves) partial[(size_t)c * nwaves + w] = s;
+}
+
+// <x, y> = sum conj(x) y, FP64 fields; partials [col][re/im][wave]
+__global__ void k_dot(SpinorPtr<P64> x, SpinorPtr<P64> y, int n, double* partial, int nwaves)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    double re = 0.0, im = 0.0;
+    if (j < n) {
+        cx<double> a[12], b[12];
+        load_spinor(x, c, j, a);
+        load_spinor(y, c, j, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            re += a[k].re * b[k].re + a[k].im * b[k].im;
+            im += a[k].re * b[k].im - a[k].im * b[k].re;
+        }
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    const int w = j >> kTileLog;
+    if ((threadIdx.x & 63) == 0 && w < nwaves) {
+        partial[((size_t)c * 2 + 0) * nwaves + w] = re;
+        partial[((size_t)c * 2 + 1) * nwaves + w] = im;
+    }
+}
+
+// x += alpha p (active and just-stopped columns); p = r + beta p (active columns)
+template <class PX, class PP, class PR>
+__global__ void k_cg_update(SpinorPtr<PX> x, SpinorPtr<PP> p, SpinorPtr<PR> r, int n, const double* alpha,
+                            const double* beta, const int* status)
+{
+    using TX = typename PX::real;
+    using TP = typename PP::real;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    const int st = status ? status[c] : COL_ACTIVE;
+    if (j >= n || (st != COL_ACTIVE && st != COL_JUST_STOPPED)) return;
+    cx<TP> pv[12];
+    load_spinor(p, c, j, pv);
+    {
+        const TX a = (TX)alpha[c];
+        cx<TX> xv[12];
+        load_spinor(x, c, j, xv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            xv[k].re = fmadd(a, (TX)pv[k].re, xv[k].re);
+            xv[k].im = fmadd(a, (TX)pv[k].im, xv[k].im);
+        }
+        store_spinor(x, c, j, xv);
+    }
+    if (st == COL_ACTIVE) {
+        const TP b = (TP)beta[c];
+        cx<typename PR::real> rv[12];
+        load_spinor(r, c, j, rv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            pv[k].re = fmadd(b, pv[k].re, (TP)rv[k].re);
+            pv[k].im = fmadd(b, pv[k].im, (TP)rv[k].im);
+        }
+        store_spinor(p, c, j, pv);
+    }
+}
+
+// y64 += x ; x = 0
+template <class PX>
+__global__ void k_accum(SpinorPtr<PX> x, SpinorPtr<P64> y, int n, const int* status, int statmask)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= n || !col_selected(status, statmask, c)) return;
+    cx<typename PX::real> xv[12];
+    cx<double> yv[12];
+    load_spinor(x, c, j, xv);
+    load_spinor(y, c, j, yv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        yv[k].re += (double)xv[k].re;
+        yv[k].im += (double)xv[k].im;
+        xv[k] = {0, 0};
+    }
+    store_spinor(y, c, j, yv);
+    store_spinor(x, c, j, xv);
+}
+
+// rs = lowp(r64) ; p = rs + beta p   (columns with flag set)
+template <class PRS, class PP>
+__global__ void k_restart(SpinorPtr<P64> r64, SpinorPtr<PRS> rs, SpinorPtr<PP> p, int n, const double* beta,
+                          const int* flag, int write_rs)
+{
+    using TP = typename PP::real;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= n || !flag[c]) return;
+    cx<double> rv[12];
+    load_spinor(r64, c, j, rv);
+    if (write_rs) {
+        cx<typename PRS::real> t[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) t[k] = {(typename PRS::real)rv[k].re, (typename PRS::real)rv[k].im};
+        store_spinor(rs, c, j, t);
+#pragma unroll
+        for (int k = 0; k < 12; k++) rv[k] = {(double)t[k].re, (double)t[k].im};
+    }
+    const TP b = (TP)beta[c];
+    cx<TP> pv[12];
+    load_spinor(p, c, j, pv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        pv[k].re = fmadd(b, pv[k].re, (TP)rv[k].re);
+        pv[k].im = fmadd(b, pv[k].im, (TP)rv[k].im);
+    }
+    store_spinor(p, c, j, pv);
+}
+
+// complex Z2 noise from SplitMix64 used as a counter-based generator:
+// output k of stream `seed` is mix(seed + (k+1) * 0x9E3779B97F4A7C15);
+// component (noise n, lexicographic site i, spin s, colour c) uses k = (n*V + i)*12 + 3s + c,
+// bit 63 -> sign of the real part, bit 62 -> sign of the imaginary part, |eta| = 1.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_z2_noise(uint64_t seed, long n0, const Geom g, int parity, SpinorPtr<P64> f)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= g.Vh) return;
+    const uint64_t V = 2 * (uint64_t)g.Vh;
+    const uint64_t lex = (uint64_t)lex_of(g, parity, j);
+    const double h = 0.70710678118654752440;
+    cx<double> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const uint64_t ctr = ((uint64_t)(n0 + c) * V + lex) * 12 + k;
+        const uint64_t z = mix64(seed + (ctr + 1) * 0x9E3779B97F4A7C15ull);
+        v[k] = {(z >> 63) & 1 ? -h : h, (z >> 62) & 1 ? -h : h};
+    }
+    store_spinor(f, c, j, v);
+}
+
+// --------------------------------------------------------------------------
+// per-column finalisation (one workgroup of 256 threads per column)
+// --------------------------------------------------------------------------
+
+__device__ double block_sum(const double* __restrict__ part, int n)
+{
+    __shared__ double w[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    return (w[0] + w[1]) + (w[2] + w[3]);
+}
+
+__global__ void k_fin_sum(const double* partial, int nwaves, double* out)
+{
+    const int c = blockIdx.x;
+    const double s = block_sum(partial + (size_t)c * nwaves, nwaves);
+    if (threadIdx.x == 0) out[c] = s;
+}
+
+__global__ void k_fin_alpha(const CgScalars s, const double* partial, int nwaves)
+{
+    const int c = blockIdx.x;
+    const int st = s.status[c];
+    if (st != COL_ACTIVE && st != COL_JUST_STOPPED) return;  // uniform per block
+    const double pAp = st == COL_ACTIVE ? block_sum(partial + (size_t)c * nwaves, nwaves) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (st == COL_JUST_STOPPED) {
+        s.status[c] = COL_STOPPED;
+        return;
+    }
+    s.pAp[c] = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+        s.alpha[c] = 0.0;
+        s.status[c] = COL_FAILED;
+    } else {
+        s.alpha[c] = s.rho[c] / pAp;
+    }
+}
+
+__global__ void k_fin_beta(const CgScalars s, const double* partial, int nwaves)
+{
+    const int c = blockIdx.x;
+    if (s.status[c] != COL_ACTIVE) return;
+    const double rho = block_sum(partial + (size_t)c * nwaves, nwaves);
+    if (threadIdx.x != 0) return;
+    s.iters[c] += 1;
+    if (!isfinite(rho)) {
+        s.status[c] = COL_FAILED;
+    } else if (rho <= s.stop2[c] || (s.delta2 > 0.0 && rho <= s.delta2 * s.rmax2[c])) {
+        s.status[c] = COL_JUST_STOPPED;  // x still takes this iteration's alpha*p
+    } else {
+        s.beta[c] = rho / s.rho[c];
+        s.rho[c] = rho;
+        if (rho > s.rmax2[c]) s.rmax2[c] = rho;
+    }
+}
+
+__global__ void k_fin_reliable(const CgScalars s, const double* partial, int nwaves)
+{
+    const int c = blockIdx.x;
+    const int st = s.status[c];
+    const bool sel = st == COL_JUST_STOPPED || st == COL_STOPPED;
+    const double r2 = sel ? block_sum(partial + (size_t)c * nwaves, nwaves) : 0.0;
+    if (threadIdx.x != 0) return;
+    s.restart[c] = 0;
+    if (!sel) return;
+    s.nrel[c] += 1;
+    if (!isfinite(r2)) {
+        s.status[c] = COL_FAILED;
+    } else if (r2 <= s.stop2[c]) {
+        s.rho[c] = r2;
+        s.status[c] = COL_DONE;
+    } else {
+        s.beta[c] = r2 / s.rho[c];
+        s.rho[c] = r2;
+        s.rmax2[c] = r2;
+        s.status[c] = COL_ACTIVE;
+        s.restart[c] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers
+// ---------------------------------------------------------------------------
+
+constexpr int kBS = 256;
+
+inline dim3 grid2(int n, int ncol) { return dim3((n + kBS - 1) / kBS, ncol); }
+
+}  // namespace
+
+hipError_t launch_links_import(const double2* canon, const Geom& g, int parity, int prec, int recon, void* const dst[4],
+                               hipStream_t st)
+{
+    const dim3 grid((g.Vh + kBS - 1) / kBS);
+#define LI(P, NC)                                                                                                 \
+    hipLaunchKernelGGL((k_links_import<P, NC>), grid, dim3(kBS), 0, st, canon, g, parity, (P::unit*)dst[0],       \
+                       (P::unit*)dst[1], (P::unit*)dst[2], (P::unit*)dst[3])
+    if (prec == PREC_F64 && recon == 18) LI(P64, 9);
+    else if (prec == PREC_F64 && recon == 12) LI(P64, 6);
+    else if (prec == PREC_F32 && recon == 18) LI(P32, 9);
+    else if (prec == PREC_F32 && recon == 12) LI(P32, 6);
+    else if (prec == PREC_F16 && recon == 12) LI(P16, 6);
+    else return hipErrorInvalidValue;
+#undef LI
+    return hipGetLastError();
+}
+
+hipError_t launch_spinor_import(const double2* canon, int ncol, const Geom& g, int parity, int prec, FieldArg dst,
+                                hipStream_t st)
+{
+    const dim3 grid = grid2(g.Vh, ncol);
+    switch (prec) {
+    case PREC_F64: hipLaunchKernelGGL(k_spinor_import<P64>, grid, dim3(kBS), 0, st, canon, g, parity, sp<P64>(dst)); break;
+    case PREC_F32: hipLaunchKernelGGL(k_spinor_import<P32>, grid, dim3(kBS), 0, st, canon, g, parity, sp<P32>(dst)); break;
+    case PREC_F16: hipLaunchKernelGGL(k_spinor_import<P16>, grid, dim3(kBS), 0, st, canon, g, parity, sp<P16>(dst)); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spinor_export(FieldArg src, int ncol, const Geom& g, int parity, int prec, double2* canon,
+                                hipStream_t st)
+{
+    const dim3 grid = grid2(g.Vh, ncol);
+    switch (prec) {
+    case PREC_F64: hipLaunchKernelGGL(k_spinor_export<P64>, grid, dim3(kBS), 0, st, sp<P64>(src), g, parity, canon); break;
+    case PREC_F32: hipLaunchKernelGGL(k_spinor_export<P32>, grid, dim3(kBS), 0, st, sp<P32>(src), g, parity, canon); break;
+    case PREC_F16: hipLaunchKernelGGL(k_spinor_export<P16>, grid, dim3(kBS), 0, st, sp<P16>(src), g, parity, canon); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int sprec, FieldArg src, int dprec, FieldArg dst, int n, int ncol, const int* status,
+                          int statmask, hipStream_t st)
+{
+    const dim3 grid = grid2(n, ncol);
+#define CV(PS, PD) hipLaunchKernelGGL((k_convert<PS, PD>), grid, dim3(kBS), 0, st, sp<PS>(src), sp<PD>(dst), n, status, statmask)
+    const int key = sprec * 3 + dprec;
+    switch (key) {
+    case PREC_F64 * 3 + PREC_F64: CV(P64, P64); break;
+    case PREC_F64 * 3 + PREC_F32: CV(P64, P32); break;
+    case PREC_F64 * 3 + PREC_F16: CV(P64, P16); break;
+    case PREC_F32 * 3 + PREC_F64: CV(P32, P64); break;
+    case PREC_F32 * 3 + PREC_F32: CV(P32, P32); break;
+    case PREC_F32 * 3 + PREC_F16: CV(P32, P16); break;
+    case PREC_F16 * 3 + PREC_F64: CV(P16, P64); break;
+    case PREC_F16 * 3 + PREC_F32: CV(P16, P32); break;
+    case PREC_F16 * 3 + PREC_F16: CV(P16, P16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef CV
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(int prec, FieldArg x, int n, int ncol, double* partial, int nwaves, hipStream_t st)
+{
+    const dim3 grid = grid2(n, ncol);
+    switch (prec) {
+    case PREC_F64: hipLaunchKernelGGL(k_norm2<P64>, grid, dim3(kBS), 0, st, sp<P64>(x), n, partial, nwaves); break;
+    case PREC_F32: hipLaunchKernelGGL(k_norm2<P32>, grid, dim3(kBS), 0, st, sp<P32>(x), n, partial, nwaves); break;
+    case PREC_F16: hipLaunchKernelGGL(k_norm2<P16>, grid, dim3(kBS), 0, st, sp<P16>(x), n, partial, nwaves); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(int prec, FieldArg x, int n, int ncol, const int* status, int statmask, hipStream_t st)
+{
+    const dim3 grid = grid2(n, ncol);
+    switch (prec) {
+    case PREC_F64: hipLaunchKernelGGL(k_zero<P64>, grid, dim3(kBS), 0, st, sp<P64>(x), n, status, statmask); break;
+    case PREC_F32: hipLaunchKernelGGL(k_zero<P32>, grid, dim3(kBS), 0, st, sp<P32>(x), n, status, statmask); break;
+    case PREC_F16: hipLaunchKernelGGL(k_zero<P16>, grid, dim3(kBS), 0, st, sp<P16>(x), n, status, statmask); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(int prec, FieldArg x, FieldArg y, int n, int ncol, double* partial, int nwaves, hipStream_t st)
+{
+    if (prec != PREC_F64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dot, grid2(n, ncol), dim3(kBS), 0, st, sp<P64>(x), sp<P64>(y), n, partial, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(int xprec, FieldArg x, int pprec, FieldArg p, int rprec, FieldArg r, int n, int ncol,
+                            const double* alpha, const double* beta, const int* status, hipStream_t st)
+{
+    const dim3 grid = grid2(n, ncol);
+#define UP(PX, PP, PR) \
+    hipLaunchKernelGGL((k_cg_update<PX, PP, PR>), grid, dim3(kBS), 0, st, sp<PX>(x), sp<PP>(p), sp<PR>(r), n, alpha, beta, status)
+    if (xprec == PREC_F64 && pprec == PREC_F64 && rprec == PREC_F64) UP(P64, P64, P64);
+    else if (xprec == PREC_F32 && pprec == PREC_F32 && rprec == PREC_F32) UP(P32, P32, P32);
+    else if (xprec == PREC_F32 && pprec == PREC_F16 && rprec == PREC_F32) UP(P32, P16, P32);
+    else return hipErrorInvalidValue;
+#undef UP
+    return hipGetLastError();
+}
+
+hipError_t launch_accum(int xprec, FieldArg x, FieldArg y64, int n, int ncol, const int* status, int statmask,
+                        hipStream_t st)
+{
+    const dim3 grid = grid2(n, ncol);
+    if (xprec == PREC_F32)
+        hipLaunchKernelGGL(k_accum<P32>, grid, dim3(kBS), 0, st, sp<P32>(x), sp<P64>(y64), n, status, statmask);
+    else if (xprec == PREC_F64)
+        hipLaunchKernelGGL(k_accum<P64>, grid, dim3(kBS), 0, st, sp<P64>(x), sp<P64>(y64), n, status, statmask);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_restart(FieldArg r64, int rsprec, FieldArg rs, int pprec, FieldArg p, int n, int ncol,
+                          const double* beta, const int* flag, hipStream_t st)
+{
+    const dim3 grid = grid2(n, ncol);
+    const int write_rs = rs.d != r64.d;
+#define RS(PRS, PP) \
+    hipLaunchKernelGGL((k_restart<PRS, PP>), grid, dim3(kBS), 0, st, sp<P64>(r64), sp<PRS>(rs), sp<PP>(p), n, beta, flag, write_rs)
+    if (rsprec == PREC_F64 && pprec == PREC_F64) RS(P64, P64);
+    else if (rsprec == PREC_F32 && pprec == PREC_F32) RS(P32, P32);
+    else if (rsprec == PREC_F32 && pprec == PREC_F16) RS(P32, P16);
+    else return hipErrorInvalidValue;
+#undef RS
+    return hipGetLastError();
+}
+
+hipError_t launch_z2_noise(uint64_t seed, long n0, const Geom& g, int parity, FieldArg dst, int ncol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_z2_noise, grid2(g.Vh, ncol), dim3(kBS), 0, st, seed, n0, g, parity, sp<P64>(dst));
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_alpha(const CgScalars& s, const double* partial, int nwaves, int ncol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fin_alpha, dim3(ncol), dim3(256), 0, st, s, partial, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_beta(const CgScalars& s, const double* partial, int nwaves, int ncol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fin_beta, dim3(ncol), dim3(256), 0, st, s, partial, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_reliable(const CgScalars& s, const double* partial, int nwaves, int ncol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fin_reliable, dim3(ncol), dim3(256), 0, st, s, partial, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_sum(const double* partial, int nwaves, int ncol, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fin_sum, dim3(ncol), dim3(256), 0, st, partial, nwaves, out);
+    return hipGetLastError();
+}
+
+}  // namespace bq
+
+namespace bq {
+namespace {
+__global__ void k_cg_init(const CgScalars s, int ncol, double tol2)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    const double r2 = s.rho[c];
+    s.stop2[c] = tol2 * r2;
+    s.rmax2[c] = r2;
+    s.iters[c] = 0;
+    s.nrel[c] = 0;
+    s.restart[c] = 0;
+    s.alpha[c] = 0.0;
+    s.beta[c] = 0.0;
+    s.status[c] = !isfinite(r2) ? COL_FAILED : (r2 > 0.0 ? COL_ACTIVE : COL_DONE);
+}
+}  // namespace
+
+hipError_t launch_cg_init(const CgScalars& s, int ncol, double tol2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_init, dim3((ncol + 63) / 64), dim3(64), 0, st, s, ncol, tol2);
+    return hipGetLastError();
+}
+}  // namespace bq

@@ -1,0 +1,510 @@
+// The hopping-term stencil (Eq. 1) with fused clover epilogues (Eq. 2).
+// Internal header: each bq_dslash_<prec>.hip instantiates it for one storage
+// precision.
+//
+// One thread owns one output site of one checkerboard and R right-hand sides.
+// For each of the 8 hops it loads the link once, and for each of its columns
+// loads the neighbour spinor, projects it to a half spinor with (1 -+ gamma_mu),
+// multiplies by U or U^dag, and accumulates the reconstructed spinor.  The
+// epilogue then applies the clover blocks and the linear combination required
+// by the caller, so that an operator application never writes the raw hop.
+#pragma once
+
+#include "bq_kernels.h"
+
+namespace bq {
+namespace dslash {
+
+// ---------------------------------------------------------------------------
+// spin projection in the chiral basis; S = -1 for (1 - gamma_mu), +1 for (1 + gamma_mu)
+// spinor index s*3 + c; half spinor index k*3 + c (k = 0, 1)
+// ---------------------------------------------------------------------------
+
+template <typename T, int S> __device__ __forceinline__ cx<T> pmi(cx<T> a) { return S > 0 ? cmuli(a) : cmulmi(a); }  // S*i*a
+
+template <typename T, int MU, int S>
+__device__ __forceinline__ void project(const cx<T> (&p)[12], cx<T> (&h)[6])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<T> p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+        if constexpr (MU == 0) {          // h0 = p0 + S i p3, h1 = p1 + S i p2
+            h[c] = cadd(p0, pmi<T, S>(p3));
+            h[3 + c] = cadd(p1, pmi<T, S>(p2));
+        } else if constexpr (MU == 1) {   // h0 = p0 - S p3, h1 = p1 + S p2
+            h[c] = S > 0 ? csub(p0, p3) : cadd(p0, p3);
+            h[3 + c] = S > 0 ? cadd(p1, p2) : csub(p1, p2);
+        } else if constexpr (MU == 2) {   // h0 = p0 + S i p2, h1 = p1 - S i p3
+            h[c] = cadd(p0, pmi<T, S>(p2));
+            h[3 + c] = csub(p1, pmi<T, S>(p3));
+        } else {                          // h0 = p0 + S p2, h1 = p1 + S p3
+            h[c] = S > 0 ? cadd(p0, p2) : csub(p0, p2);
+            h[3 + c] = S > 0 ? cadd(p1, p3) : csub(p1, p3);
+        }
+    }
+}
+
+// acc += (1 + S gamma_mu) psi, given h = the projected (and colour-rotated) half spinor
+template <typename T, int MU, int S>
+__device__ __forceinline__ void reconstruct_add(cx<T> (&acc)[12], const cx<T> (&h)[6])
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<T> h0 = h[c], h1 = h[3 + c];
+        acc[c] = cadd(acc[c], h0);
+        acc[3 + c] = cadd(acc[3 + c], h1);
+        if constexpr (MU == 0) {          // rows 2,3 = -S i h1, -S i h0
+            acc[6 + c] = csub(acc[6 + c], pmi<T, S>(h1));
+            acc[9 + c] = csub(acc[9 + c], pmi<T, S>(h0));
+        } else if constexpr (MU == 1) {   // rows 2,3 = S h1, -S h0
+            acc[6 + c] = S > 0 ? cadd(acc[6 + c], h1) : csub(acc[6 + c], h1);
+            acc[9 + c] = S > 0 ? csub(acc[9 + c], h0) : cadd(acc[9 + c], h0);
+        } else if constexpr (MU == 2) {   // rows 2,3 = -S i h0, S i h1
+            acc[6 + c] = csub(acc[6 + c], pmi<T, S>(h0));
+            acc[9 + c] = cadd(acc[9 + c], pmi<T, S>(h1));
+        } else {                          // rows 2,3 = S h0, S h1
+            acc[6 + c] = S > 0 ? cadd(acc[6 + c], h0) : csub(acc[6 + c], h0);
+            acc[9 + c] = S > 0 ? cadd(acc[9 + c], h1) : csub(acc[9 + c], h1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// links
+// ---------------------------------------------------------------------------
+
+template <class P, int RECON>
+__device__ __forceinline__ void load_link(const typename P::unit* __restrict__ U, int j, cx<typename P::real> (&u)[9])
+{
+    using T = typename P::real;
+    if constexpr (RECON == 18) {
+        CxIO<P, 9>::load_cached(U, j, u);
+    } else {
+        cx<T> r[6];
+        CxIO<P, 6>::load_cached(U, j, r);
+#pragma unroll
+        for (int k = 0; k < 6; k++) u[k] = r[k];
+        // third row of an SU(3) matrix: conj(row0 x row1)
+        cx<T> w0 = csub(cmul(r[1], r[5]), cmul(r[2], r[4]));
+        cx<T> w1 = csub(cmul(r[2], r[3]), cmul(r[0], r[5]));
+        cx<T> w2 = csub(cmul(r[0], r[4]), cmul(r[1], r[3]));
+        u[6] = {w0.re, -w0.im};
+        u[7] = {w1.re, -w1.im};
+        u[8] = {w2.re, -w2.im};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void mul_U(const cx<T> (&u)[9], const cx<T> (&h)[6], cx<T> (&y)[6])
+{
+#pragma unroll
+    for (int k = 0; k < 2; k++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<T> s = cmul(u[a * 3 + 0], h[k * 3 + 0]);
+            s = cmac(s, u[a * 3 + 1], h[k * 3 + 1]);
+            s = cmac(s, u[a * 3 + 2], h[k * 3 + 2]);
+            y[k * 3 + a] = s;
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void mul_Ud(const cx<T> (&u)[9], const cx<T> (&h)[6], cx<T> (&y)[6])
+{
+#pragma unroll
+    for (int k = 0; k < 2; k++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            cx<T> s = {T(0), T(0)};
+            s = cmacc(s, u[0 * 3 + a], h[k * 3 + 0]);
+            s = cmacc(s, u[1 * 3 + a], h[k * 3 + 1]);
+            s = cmacc(s, u[2 * 3 + a], h[k * 3 + 2]);
+            y[k * 3 + a] = s;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// clover: two packed Hermitian 6x6 blocks per site, 18 complex each:
+//   [0..2]  diagonal (d0 + i d1, d2 + i d3, d4 + i d5)
+//   [3..17] strictly lower triangle A[i][j], i > j, at 3 + i(i-1)/2 + j
+// block 0 acts on spins 0,1 (components 0..5), block 1 on spins 2,3.
+// ---------------------------------------------------------------------------
+
+template <class P>
+__device__ __forceinline__ void load_clover_block(const typename P::unit* __restrict__ C, int j, int blk,
+                                                  cx<typename P::real> (&c)[18])
+{
+    if constexpr (P::id == PREC_F16) {
+#pragma unroll
+        for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(C[toff(j, blk * 9 + u, 18)], c[2 * u], c[2 * u + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+            auto t = C[toff(j, blk * 18 + k, 36)];
+            c[k] = {t.x, t.y};
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void clover_mul(const cx<T> (&c)[18], const cx<T>* x, cx<T>* y)
+{
+    const T d[6] = {c[0].re, c[0].im, c[1].re, c[1].im, c[2].re, c[2].im};
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] = cscale(d[i], x[i]);
+#pragma unroll
+    for (int i = 1; i < 6; i++)
+#pragma unroll
+        for (int jj = 0; jj < i; jj++) {
+            const cx<T> A = c[3 + i * (i - 1) / 2 + jj];
+            y[i] = cmac(y[i], A, x[jj]);
+            y[jj] = cmacc(y[jj], A, x[i]);
+        }
+}
+
+// half of a spinor (block `blk`: complex 6*blk .. 6*blk+5) for FP32/FP64 storage
+template <class P>
+__device__ __forceinline__ void load_spinor_part(const SpinorPtr<P>& f, int col, int j, int blk,
+                                                 cx<typename P::real> (&v)[6])
+{
+    if constexpr (P::id == PREC_F16) {
+        const uint2* b = f.d + col * f.cstride;
+        float s = f.s[col * f.sstride + j];
+#pragma unroll
+        for (int u = 0; u < 3; u++) {
+            CxIO<P16, 2>::unpack(b[toff(j, blk * 3 + u, 6)], v[2 * u], v[2 * u + 1]);
+            v[2 * u] = cscale(s, v[2 * u]);
+            v[2 * u + 1] = cscale(s, v[2 * u + 1]);
+        }
+    } else {
+        const typename P::unit* b = f.d + col * f.cstride;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            auto t = b[toff(j, blk * 6 + k, 12)];
+            v[k] = {t.x, t.y};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel
+// ---------------------------------------------------------------------------
+
+template <class P, class PR>
+struct Args {
+    Geom g;
+    int parity, ncol;
+    const typename P::unit* U[8];
+    SpinorPtr<P> in, out, v;
+    SpinorPtr<PR> rin, rout;
+    const typename P::unit* clov;
+    const double* alpha;
+    double* partial;
+    int nwaves, pstride;
+    const int* status;
+    int statmask;
+    typename P::real ef, eb, ef_bc, eb_bc;  // time coefficients, without / with the boundary sign
+    typename P::real f, a;
+};
+
+// End of one hop's phase.  Without it the compiler issues the loads of all
+// eight hops first and sinks their arithmetic to the end of the kernel, which
+// keeps every loaded value live and spills.  Pinning the accumulators in
+// registers forces each hop's arithmetic to finish before the next hop's
+// loads are issued.
+template <typename T, int R>
+__device__ __forceinline__ void phase_end(const bool (&act)[R], cx<T> (&acc)[R][12])
+{
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[r][k].re), "+v"(acc[r][k].im));
+    asm volatile("" ::: "memory");
+}
+
+template <class P, class PR, int R, int DAG, int RECON, int MU>
+__device__ __forceinline__ void hop_dir(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                        cx<typename P::real> (&acc)[R][12])
+{
+    using T = typename P::real;
+    constexpr int SF = DAG ? +1 : -1;  // forward term projector (1 + SF gamma_mu)
+    constexpr int SB = -SF;
+    cx<T> u[9];
+    {   // U_mu(x) (1 + SF gamma_mu) psi(x + mu)
+        const int jf = nbr(A.g, s, MU, +1);
+        load_link<P, RECON>(A.U[A.parity * 4 + MU], s.j, u);
+        T coef = T(1);
+        if constexpr (MU == 3) coef = (s.t == A.g.L[3] - 1) ? A.ef_bc : A.ef;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (!act[r]) continue;
+            cx<T> p[12], h[6], y[6];
+            load_spinor(A.in, c0 + r, jf, p);
+            project<T, MU, SF>(p, h);
+            if constexpr (MU == 3) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) h[k] = cscale(coef, h[k]);
+            }
+            mul_U(u, h, y);
+            reconstruct_add<T, MU, SF>(acc[r], y);
+        }
+    }
+    phase_end(act, acc);
+    {   // U_mu(x - mu)^dag (1 + SB gamma_mu) psi(x - mu)
+        const int jb = nbr(A.g, s, MU, -1);
+        load_link<P, RECON>(A.U[(1 - A.parity) * 4 + MU], jb, u);
+        T coef = T(1);
+        if constexpr (MU == 3) coef = (s.t == 0) ? A.eb_bc : A.eb;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (!act[r]) continue;
+            cx<T> p[12], h[6], y[6];
+            load_spinor(A.in, c0 + r, jb, p);
+            project<T, MU, SB>(p, h);
+            if constexpr (MU == 3) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) h[k] = cscale(coef, h[k]);
+            }
+            mul_Ud(u, h, y);
+            reconstruct_add<T, MU, SB>(acc[r], y);
+        }
+    }
+    phase_end(act, acc);
+}
+
+template <class P, class PR, int R, int DAG, int EPI, int RECON>
+__global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
+{
+    using T = typename P::real;
+    using TR = typename PR::real;
+    const int ngroups = (A.ncol + R - 1) / R;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int sb = lb / ngroups;
+    const int grp = lb - sb * ngroups;
+    const int j = sb * blockDim.x + threadIdx.x;
+    const int c0 = grp * R;
+
+    bool act[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int c = c0 + r;
+        act[r] = j < A.g.Vh && c < A.ncol && col_selected(A.status, A.statmask, c);
+        any |= act[r];
+    }
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) nrm[r] = 0.0;
+
+    if (any) {
+        const Site s = site_of(A.g, A.parity, j);
+        cx<T> acc[R][12];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
+
+        hop_dir<P, PR, R, DAG, RECON, 0>(A, s, act, c0, acc);
+        hop_dir<P, PR, R, DAG, RECON, 1>(A, s, act, c0, acc);
+        hop_dir<P, PR, R, DAG, RECON, 2>(A, s, act, c0, acc);
+        hop_dir<P, PR, R, DAG, RECON, 3>(A, s, act, c0, acc);
+
+        if constexpr (EPI == EPI_HOP || EPI == EPI_TINV) {
+            // w = a*v + f*hop
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (!act[r]) continue;
+                if (A.v.d != nullptr) {
+                    cx<T> v[12];
+                    load_spinor(A.v, c0 + r, j, v);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) acc[r][k] = caxpy(A.f, acc[r][k], cscale(A.a, v[k]));
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; k++) acc[r][k] = cscale(A.f, acc[r][k]);
+                }
+            }
+            if constexpr (EPI == EPI_TINV) {
+#pragma unroll
+                for (int blk = 0; blk < 2; blk++) {
+                    cx<T> cb[18];
+                    load_clover_block<P>(A.clov, j, blk, cb);
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        if (!act[r]) continue;
+                        cx<T> x[6];
+#pragma unroll
+                        for (int k = 0; k < 6; k++) x[k] = acc[r][blk * 6 + k];
+                        clover_mul(cb, x, &acc[r][blk * 6]);
+                    }
+                    phase_end(act, acc);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (act[r]) store_spinor(A.out, c0 + r, j, acc[r]);
+        } else if constexpr (EPI == EPI_TV) {
+            // out = C v + f*hop, assembled in place (FP16 storage needs the whole site for its scale)
+#pragma unroll
+            for (int blk = 0; blk < 2; blk++) {
+                cx<T> cb[18];
+                load_clover_block<P>(A.clov, j, blk, cb);
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (!act[r]) continue;
+                    cx<T> x[6], y[6];
+                    load_spinor_part(A.v, c0 + r, j, blk, x);
+                    clover_mul(cb, x, y);
+#pragma unroll
+                    for (int k = 0; k < 6; k++) acc[r][blk * 6 + k] = caxpy(A.f, acc[r][blk * 6 + k], y[k]);
+                }
+                phase_end(act, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (!act[r]) continue;
+                store_spinor(A.out, c0 + r, j, acc[r]);
+                double n = 0.0;
+#pragma unroll
+                for (int k = 0; k < 12; k++) n += (double)acc[r][k].re * acc[r][k].re + (double)acc[r][k].im * acc[r][k].im;
+                nrm[r] = n;
+            }
+        } else {
+            // w = C v + f*hop ; r_out = r_in - alpha*w, one clover block (half spinor) at a time
+            static_assert(PR::id != PREC_F16, "the residual is kept in FP32 or FP64");
+#pragma unroll
+            for (int blk = 0; blk < 2; blk++) {
+                cx<T> cb[18];
+                load_clover_block<P>(A.clov, j, blk, cb);
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (!act[r]) continue;
+                    const int c = c0 + r;
+                    const TR al = A.alpha ? (TR)A.alpha[c] : TR(1);
+                    cx<T> x[6], y[6];
+                    load_spinor_part(A.v, c, j, blk, x);
+                    clover_mul(cb, x, y);
+                    cx<TR> rv[6];
+                    load_spinor_part(A.rin, c, j, blk, rv);
+                    typename PR::unit* rb = A.rout.d + c * A.rout.cstride;
+                    double n = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 6; k++) {
+                        const cx<T> w = caxpy(A.f, acc[r][blk * 6 + k], y[k]);
+                        rv[k].re = fmadd(-al, (TR)w.re, rv[k].re);
+                        rv[k].im = fmadd(-al, (TR)w.im, rv[k].im);
+                        rb[toff(j, blk * 6 + k, 12)] = {rv[k].re, rv[k].im};
+                        n += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
+                    }
+                    nrm[r] += n;
+                }
+                phase_end(act, acc);
+            }
+        }
+    }
+
+    if constexpr (EPI == EPI_TV || EPI == EPI_TVR) {
+        if (A.partial != nullptr) {
+            const int wave = j >> kTileLog;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const double t = wave_sum(nrm[r]);
+                const int c = c0 + r;
+                if ((threadIdx.x & 63) == 0 && c < A.ncol && wave < A.nwaves && col_selected(A.status, A.statmask, c))
+                    A.partial[(size_t)c * A.pstride + wave] = t;
+            }
+        }
+    }
+}
+
+template <class P>
+SpinorPtr<P> sp(const FieldArg& f)
+{
+    return SpinorPtr<P>{(typename P::unit*)f.d, f.s, f.cstride, f.sstride};
+}
+
+template <class P, class PR, int R, int DAG, int EPI, int RECON>
+hipError_t launch_t(const HopLaunch& L, hipStream_t st)
+{
+    using T = typename P::real;
+    Args<P, PR> A;
+    A.g = L.g;
+    A.parity = L.parity;
+    A.ncol = L.ncol;
+    for (int k = 0; k < 8; k++) A.U[k] = (const typename P::unit*)L.U[k];
+    A.in = sp<P>(L.in);
+    A.out = sp<P>(L.out);
+    A.v = sp<P>(L.v);
+    A.rin = sp<PR>(L.r_in);
+    A.rout = sp<PR>(L.r_out);
+    A.clov = (const typename P::unit*)L.clov;
+    A.alpha = L.alpha;
+    A.partial = L.partial;
+    A.nwaves = L.nwaves;
+    A.pstride = L.pstride ? L.pstride : L.nwaves;
+    A.status = L.status;
+    A.statmask = L.statmask;
+    A.ef = (T)L.ef;
+    A.eb = (T)L.eb;
+    A.ef_bc = (T)(L.ef * L.tbc);
+    A.eb_bc = (T)(L.eb * L.tbc);
+    A.f = (T)L.f;
+    A.a = (T)L.a;
+    const int nsb = (L.g.Vh + L.bs - 1) / L.bs;
+    const int ngroups = (L.ncol + R - 1) / R;
+    hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON>), dim3(nsb * ngroups), dim3(L.bs), 0, st, A);
+    return hipGetLastError();
+}
+
+template <class P, class PR, int R, int DAG, int EPI>
+hipError_t by_recon(const HopLaunch& L, hipStream_t st)
+{
+    if constexpr (P::id == PREC_F16) {
+        if (L.recon != 12) return hipErrorInvalidValue;
+        return launch_t<P, PR, R, DAG, EPI, 12>(L, st);
+    } else {
+        if (L.recon == 12) return launch_t<P, PR, R, DAG, EPI, 12>(L, st);
+        if (L.recon == 18) return launch_t<P, PR, R, DAG, EPI, 18>(L, st);
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class P, class PR, int R, int DAG>
+hipError_t by_epi(const HopLaunch& L, hipStream_t st)
+{
+    switch (L.epi) {
+    case EPI_HOP: return by_recon<P, PR, R, DAG, EPI_HOP>(L, st);
+    case EPI_TINV: return by_recon<P, PR, R, DAG, EPI_TINV>(L, st);
+    case EPI_TV: return by_recon<P, PR, R, DAG, EPI_TV>(L, st);
+    case EPI_TVR: return by_recon<P, PR, R, DAG, EPI_TVR>(L, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class P, class PR, int R>
+hipError_t by_dag(const HopLaunch& L, hipStream_t st)
+{
+    return L.dagger ? by_epi<P, PR, R, 1>(L, st) : by_epi<P, PR, R, 0>(L, st);
+}
+
+// columns per thread: FP64 keeps R <= 2 (R >= 3 exceeds 256 VGPRs and spills)
+template <class P> constexpr int max_R() { return P::id == PREC_F64 ? 2 : 4; }
+
+template <class P, class PR>
+hipError_t by_R(const HopLaunch& L, hipStream_t st)
+{
+    switch (L.R) {
+    case 1: return by_dag<P, PR, 1>(L, st);
+    case 2: return by_dag<P, PR, 2>(L, st);
+    }
+    if constexpr (max_R<P>() >= 4) {
+        switch (L.R) {
+        case 3: return by_dag<P, PR, 3>(L, st);
+        case 4: return by_dag<P, PR, 4>(L, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dslash
+}  // namespace bq

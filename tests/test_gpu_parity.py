@@ -1,0 +1,283 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Tolerances (relative to the largest reference element):
+  FP64 1e-12 (field agreement bar), FP32 1e-5, FP16 4e-3.
+The FP16 bound follows from binary16 rounding (unit roundoff 2^-11 = 4.9e-4)
+of links, clover entries and per-site-scaled spinors, accumulated over the
+8 hops and the clover matvec with FP32 arithmetic.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1711_03836_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5, 2: 4e-3}
+# 6x4x4x6: V/2 = 288 sites = 4.5 wavefronts (several tiles and a ragged tail); mu != 0, antiperiodic t
+DIMS = (6, 4, 4, 6)
+KAPPA, CSW, MU = 0.124, 1.5, 0.1
+
+
+@pytest.fixture(scope="module")
+def bq():
+    from paper_1711_03836_amd import bqhip
+    return bqhip
+
+
+@pytest.fixture(scope="module")
+def setup(bq):
+    ctx = bq.Context(0)
+    U = inputs.gauge_field(DIMS, 0.3, seed=101)
+    G = bq.Gauge(ctx, DIMS, U, t_bc=-1)
+    op = bq.Op(G, KAPPA, CSW, MU)
+    ref = orc.Operator(DIMS, U, KAPPA, CSW, mu=MU, t_bc=-1)
+    return ctx, G, op, ref, U
+
+
+def maxrel(got, want):
+    return np.abs(got - want).max() / np.abs(want).max()
+
+
+def oracle_apply(ref, kind, bq, psi):
+    """Reference for one column (V, 4, 3)."""
+    K = bq
+    if kind == K.BQ_OP_M:
+        return ref.M(psi)
+    if kind == K.BQ_OP_MDAG:
+        return ref.M(psi, dagger=True)
+    if kind == K.BQ_OP_MDAGM:
+        return ref.M(ref.M(psi), dagger=True)
+    if kind == K.BQ_OP_MHAT:
+        return ref.Mhat(ref.odd(psi))
+    if kind == K.BQ_OP_MHATDAG:
+        return ref.Mhat(ref.odd(psi), dagger=True)
+    if kind == K.BQ_OP_MHATDAG_MHAT:
+        return ref.Mhat(ref.Mhat(ref.odd(psi)), dagger=True)
+    if kind in (K.BQ_OP_DEO, K.BQ_OP_DEO_DAG):
+        return ref.even(ref.hop(ref.odd(psi), dagger=kind == K.BQ_OP_DEO_DAG))
+    if kind in (K.BQ_OP_DOE, K.BQ_OP_DOE_DAG):
+        return ref.odd(ref.hop(ref.even(psi), dagger=kind == K.BQ_OP_DOE_DAG))
+    if kind in (K.BQ_OP_K1, K.BQ_OP_K1_DAG):
+        h = ref.even(ref.hop(ref.odd(psi), dagger=kind == K.BQ_OP_K1_DAG))
+        return orc.clover_apply(ref.dims, ref.Tinv, h, parity_mask=1)
+    if kind == K.BQ_OP_CLOVER:
+        return orc.clover_apply(ref.dims, ref.T, psi)
+    if kind == K.BQ_OP_CLOVER_INV:
+        return orc.clover_apply(ref.dims, ref.Tinv, ref.even(psi), parity_mask=1)
+    raise ValueError(kind)
+
+
+KINDS = ["BQ_OP_M", "BQ_OP_MDAG", "BQ_OP_MDAGM", "BQ_OP_MHAT", "BQ_OP_MHATDAG", "BQ_OP_MHATDAG_MHAT", "BQ_OP_DEO",
+         "BQ_OP_DOE", "BQ_OP_DEO_DAG", "BQ_OP_DOE_DAG", "BQ_OP_K1", "BQ_OP_K1_DAG", "BQ_OP_CLOVER",
+         "BQ_OP_CLOVER_INV"]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("kind_name", KINDS)
+def test_operator_parity(bq, setup, kind_name, prec):
+    ctx, G, op, ref, U = setup
+    kind = getattr(bq, kind_name)
+    si, so = bq.OP_SUBSETS[kind]
+    nrhs = 3
+    psi = inputs.gaussian_spinor(DIMS, nrhs, seed=7 + prec)
+    fi = bq.Field(ctx, DIMS, si, prec, nrhs)
+    fo = bq.Field(ctx, DIMS, so, prec, nrhs)
+    fi.put(psi)
+    op.apply(kind, fi, fo)
+    got = fo.get()
+    mask = {bq.BQ_EVEN: ref.parity == 0, bq.BQ_ODD: ref.parity == 1, bq.BQ_FULL: np.ones(ref.V, bool)}[so]
+    for c in range(nrhs):
+        want = oracle_apply(ref, kind, bq, psi[c])
+        err = maxrel(got[c][mask], want[mask])
+        print(f"{kind_name} prec={prec} col={c} maxrel={err:.3e}", flush=True)
+        assert err < TOL[prec], (kind_name, prec, c, err)
+        # sites outside the output subset are not written
+        assert np.all(got[c][~mask] == 0)
+
+
+@pytest.mark.parametrize("prec,recon,R,bs", [(0, 12, 1, 64), (0, 18, 2, 128), (0, 12, 2, 512), (1, 12, 3, 256),
+                                             (1, 18, 4, 64), (1, 12, 1, 512), (2, 12, 2, 128), (2, 12, 4, 256)])
+def test_kernel_configurations(bq, setup, prec, recon, R, bs):
+    """Every link form, column tile and block size gives the oracle's result (12 columns, K1 and Mhat)."""
+    ctx, G, op, ref, U = setup
+    nrhs = 12
+    ctx.tune_set(prec, nrhs, recon, R, bs)
+    psi = inputs.gaussian_spinor(DIMS, nrhs, seed=55)
+    for kind in (bq.BQ_OP_K1, bq.BQ_OP_MHATDAG_MHAT):
+        si, so = bq.OP_SUBSETS[kind]
+        fi = bq.Field(ctx, DIMS, si, prec, nrhs)
+        fo = bq.Field(ctx, DIMS, so, prec, nrhs)
+        fi.put(psi)
+        op.apply(kind, fi, fo)
+        got = fo.get()
+        mask = ref.parity == (0 if so == bq.BQ_EVEN else 1)
+        for c in (0, 5, 11):
+            want = oracle_apply(ref, kind, bq, psi[c])
+            assert maxrel(got[c][mask], want[mask]) < TOL[prec]
+
+
+def test_plaquette(bq, setup):
+    ctx, G, op, ref, U = setup
+    assert abs(G.plaquette() - orc.plaquette(DIMS, U)) < 1e-14
+
+
+def test_field_roundtrip_and_untouched_sites(bq, setup):
+    ctx = setup[0]
+    psi = inputs.gaussian_spinor(DIMS, 2, seed=3)
+    f = bq.Field(ctx, DIMS, bq.BQ_ODD, bq.BQ_F64, 2)
+    f.put(psi)
+    out = np.full_like(psi, 7.0)
+    f.get(out)
+    par = orc.site_parity(DIMS)
+    assert np.array_equal(out[:, par == 1], psi[:, par == 1])
+    assert np.all(out[:, par == 0] == 7.0)
+
+
+def test_clover_not_hpd(bq, setup):
+    ctx, G = setup[0], setup[1]
+    with pytest.raises(bq.BqError) as e:
+        bq.Op(G, 5.0, 10.0, 0.0)
+    assert e.value.code == bq.BQ_ERR_CLOVER_NOT_HPD
+
+
+def test_gauge_busy_and_invalid(bq, setup):
+    ctx, G = setup[0], setup[1]
+    with pytest.raises(bq.BqError) as e:
+        G.close()
+    assert e.value.code == bq.BQ_ERR_BUSY
+    with pytest.raises(bq.BqError) as e:
+        bq.Field(ctx, (4, 4, 3, 4), bq.BQ_FULL, 0, 1)
+    assert e.value.code == bq.BQ_ERR_INVALID
+
+
+# ---------------------------------------------------------------------------
+# solves
+# ---------------------------------------------------------------------------
+
+def _solve(bq, op, dims, b, system, prec, tol, nrhs, use_graph=False, chunk=8):
+    sub = bq.BQ_ODD if system == bq.BQ_SYS_NORMAL else bq.BQ_FULL
+    fb = bq.Field(op.ctx, dims, sub, 0, nrhs)
+    fx = bq.Field(op.ctx, dims, sub, 0, nrhs)
+    fb.put(b)
+    rc, info = op.solve(fb, fx, tol, system=system, inner_prec=prec, use_graph=use_graph, chunk=chunk)
+    return fx.get(), info
+
+
+def test_config0_full_normal_4444(bq):
+    """4^4, unpreconditioned CG on M^dag M, kappa=0.12, c_SW=1.0, U=exp(0.3 i H), tol 1e-12."""
+    dims = (4, 4, 4, 4)
+    U = inputs.gauge_field(dims, 0.3, seed=2024)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.12, 1.0, 0.0)
+    ref = orc.Operator(dims, U, 0.12, 1.0)
+    b = inputs.gaussian_spinor(dims, 1, seed=1)
+    x, info = _solve(bq, op, dims, b, bq.BQ_SYS_FULL_NORMAL, 0, 1e-12, 1)
+    r = b[0] - ref.M(ref.M(x[0]), dagger=True)
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b[0]) * 1.01
+    assert info[0]["converged"] and info[0]["true_rel_resid"] <= 1e-12
+    xo, it = ref.cg(b[0], 0, 1e-12, 10000)
+    assert abs(info[0]["iters"] - it) <= 2 + it // 50
+    assert np.linalg.norm(x[0] - xo) / np.linalg.norm(xo) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_eo_solve_sys_m(bq, setup, prec):
+    """M x = b through the Schur system; oracle recomputes |b - M x|."""
+    ctx, G, op, ref, U = setup
+    b = inputs.gaussian_spinor(DIMS, 2, seed=31)
+    x, info = _solve(bq, op, DIMS, b, bq.BQ_SYS_M, prec, 1e-10, 2)
+    for c in range(2):
+        assert info[c]["converged"], info[c]
+        full = np.linalg.norm(b[c] - ref.M(x[c])) / np.linalg.norm(b[c])
+        assert abs(full - info[c]["full_rel_resid"]) <= 1e-3 * full + 1e-14
+        bh = ref.prepare(b[c])
+        bp = ref.Mhat(bh, dagger=True)
+        xo = ref.odd(x[c])
+        tr = np.linalg.norm(bp - ref.Mhat(ref.Mhat(xo), dagger=True)) / np.linalg.norm(bp)
+        assert tr <= 1e-10 * 1.05, tr
+        if prec > 0:
+            assert info[c]["reliable_updates"] >= 1
+
+
+def test_normal_solve_and_graph(bq, setup):
+    ctx, G, op, ref, U = setup
+    b = inputs.gaussian_spinor(DIMS, 3, seed=41)
+    par = orc.site_parity(DIMS)
+    b[:, par == 0] = 0
+    x1, i1 = _solve(bq, op, DIMS, b, bq.BQ_SYS_NORMAL, 1, 1e-10, 3, use_graph=False)
+    x2, i2 = _solve(bq, op, DIMS, b, bq.BQ_SYS_NORMAL, 1, 1e-10, 3, use_graph=True)
+    assert np.array_equal(x1, x2)  # graph replay = direct launches, bit for bit
+    assert [a["iters"] for a in i1] == [a["iters"] for a in i2]
+    for c in range(3):
+        r = b[c] - ref.Mhat(ref.Mhat(x1[c]), dagger=True)
+        assert np.linalg.norm(r[par == 1]) <= 1.05e-10 * np.linalg.norm(b[c])
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_batch_invariance(bq, setup, prec):
+    """A column's solution is the same alone and inside a batch (bit for bit)."""
+    ctx, G, op, ref, U = setup
+    b = inputs.gaussian_spinor(DIMS, 4, seed=77)
+    xa, ia = _solve(bq, op, DIMS, b[1:2], bq.BQ_SYS_M, prec, 1e-10, 1)
+    xb, ib = _solve(bq, op, DIMS, b, bq.BQ_SYS_M, prec, 1e-10, 4)
+    assert np.array_equal(xa[0], xb[1])
+    assert ia[0]["iters"] == ib[1]["iters"]
+
+
+def test_nonconverged_and_nonfinite(bq, setup):
+    ctx, G, op, ref, U = setup
+    b = inputs.gaussian_spinor(DIMS, 1, seed=5)
+    fb = bq.Field(ctx, DIMS, bq.BQ_FULL, 0, 1)
+    fx = bq.Field(ctx, DIMS, bq.BQ_FULL, 0, 1)
+    fb.put(b)
+    rc, info = op.solve(fb, fx, 1e-10, system=bq.BQ_SYS_M, maxiter=8, chunk=4, raise_on_error=False)
+    assert rc == bq.BQ_ERR_NOT_CONVERGED and not info[0]["converged"] and info[0]["iters"] == 8
+    b[0, 3, 1, 1] = np.nan
+    fb.put(b)
+    rc, info = op.solve(fb, fx, 1e-10, system=bq.BQ_SYS_M, raise_on_error=False)
+    assert rc == bq.BQ_ERR_NONFINITE
+
+
+def test_zero_source(bq, setup):
+    ctx, G, op, ref, U = setup
+    b = np.zeros((1, ref.V, 4, 3), complex)
+    x, info = _solve(bq, op, DIMS, b, bq.BQ_SYS_M, 1, 1e-10, 1)
+    assert np.all(x == 0) and info[0]["converged"]
+
+
+def test_point_sources_mu(bq):
+    """12 spin-colour point sources with mu = 0.1 in one batch (small lattice of the 32^3x64 workload's kind)."""
+    dims = (4, 4, 4, 8)
+    U = inputs.gauge_field(dims, 0.2, seed=9)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.124, 1.5, 0.1)
+    ref = orc.Operator(dims, U, 0.124, 1.5, mu=0.1)
+    b = inputs.point_sources(dims)
+    x, info = _solve(bq, op, dims, b, bq.BQ_SYS_M, 2, 1e-10, 12)
+    for c in range(12):
+        assert info[c]["converged"]
+        assert np.linalg.norm(b[c] - ref.M(x[c])) / np.linalg.norm(b[c]) < 1e-7
+
+
+def test_trace_per_noise(bq, setup):
+    ctx, G, op, ref, U = setup
+    t1, t2, info = op.trace(seed=2718, nnoise=5, block=2, tol=1e-10, inner_prec=bq.BQ_F32)
+    for n in range(5):
+        eta = orc.z2_noise(DIMS, 2718, n)
+        x1, _ = ref.solve_M(eta, 1e-12)
+        x2, _ = ref.solve_M(x1, 1e-12)
+        w1 = np.vdot(eta.ravel(), x1.ravel())
+        w2 = np.vdot(eta.ravel(), x2.ravel())
+        assert abs(t1[n] - w1) < 1e-6 * abs(w1)
+        assert abs(t2[n] - w2) < 1e-6 * abs(w2)
+
+
+def test_hbm_budget(bq):
+    ctx = bq.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(bq.BqError) as e:
+        bq.Field(ctx, (8, 8, 8, 8), bq.BQ_FULL, 0, 4)
+    assert e.value.code == bq.BQ_ERR_OOM
