@@ -194,9 +194,10 @@ int bq_solve_stats_get(bq_op op, bq_solve_stats* out);
  * *bytes = algorithmic bytes one launch must move (each input read once). */
 int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void* stream, double* ms, double* bytes);
 
-/* Kernel configuration used for a given precision and column count (filled in
- * by the autotuner on first use, or set explicitly).  recon: 12 or 18 reals per
- * link; R: columns per thread; bs: threads per block. */
+/* Stencil configuration used for a given precision and column count (set by
+ * bq_autotune or explicitly; otherwise a default).  recon: 12 or 18 reals per
+ * link; R: columns per thread; bs: sites per workgroup (64, 128, 256 or 512;
+ * the column groups of those sites run in the same workgroup, up to 512 threads). */
 int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs);
 int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs);
 /* Time the candidate configurations for (op's lattice, prec, nrhs) on op and keep the fastest. */

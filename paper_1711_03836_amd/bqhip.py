@@ -24,7 +24,8 @@ except Exception:  # pragma: no cover - torch is part of the environment
     torch = None
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbqhip.so")
+# BQHIP_LIBRARY selects another build of the same library (e.g. a variant under test)
+LIB_PATH = os.environ.get("BQHIP_LIBRARY") or os.path.join(HERE, "libbqhip.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python paper_1711_03836_amd/build.py` "

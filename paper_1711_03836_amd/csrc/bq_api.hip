@@ -98,10 +98,17 @@ struct bq_context_s {
     uint64_t used = 0;
     hipStream_t stream = nullptr;
     std::map<std::pair<int, int>, Tune> tune;  // (prec, ncol) -> config
+    unsigned nalloc = 0;                       // allocation counter (skews)
 };
+
+// Every array is laid out with its own small skew (an odd number of 128-byte lines): the
+// fields, link and clover arrays have power-of-two sizes on power-of-two lattices, and
+// unskewed the same tile of all of them would fall into the same L2 sets.
+static const size_t kSkew = 17 * 128;
 
 struct DevBuf {
     bq_context ctx = nullptr;
+    void* raw = nullptr;
     void* p = nullptr;
     size_t bytes = 0;
     DevBuf() = default;
@@ -110,11 +117,11 @@ struct DevBuf {
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) {
-            (void)hipFree(p);
+        if (raw) {
+            (void)hipFree(raw);
             ctx->used -= bytes;
         }
-        p = nullptr;
+        raw = p = nullptr;
         bytes = 0;
     }
     int alloc(bq_context c, size_t n)
@@ -122,26 +129,32 @@ struct DevBuf {
         release();
         ctx = c;
         if (n == 0) return BQ_OK;
-        if (c->used + n > c->budget)
-            return fail(BQ_ERR_OOM, "HBM budget exceeded: %zu bytes requested, %llu of %llu in use", n,
+        const size_t skew = (size_t)(c->nalloc++ % 31) * kSkew;
+        const size_t total = n + 31 * kSkew;
+        if (c->used + total > c->budget)
+            return fail(BQ_ERR_OOM, "HBM budget exceeded: %zu bytes requested, %llu of %llu in use", total,
                         (unsigned long long)c->used, (unsigned long long)c->budget);
-        hipError_t e = hipMalloc(&p, n);
+        hipError_t e = hipMalloc(&raw, total);
         if (e != hipSuccess) {
-            p = nullptr;
-            return fail(BQ_ERR_OOM, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+            raw = nullptr;
+            return fail(BQ_ERR_OOM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
         }
         // zero on the context stream and wait, so that work on any stream sees zeros
-        e = hipMemsetAsync(p, 0, n, c->stream);
+        e = hipMemsetAsync(raw, 0, total, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(BQ_ERR_DEVICE, "zeroing new device memory failed: %s", hipGetErrorString(e));
-        bytes = n;
-        c->used += n;
+        p = (char*)raw + skew;
+        bytes = total;
+        c->used += total;
         return BQ_OK;
     }
     template <typename T> T* as() const { return (T*)p; }
 };
 
 static size_t unit_bytes(int prec) { return prec == PREC_F64 ? 16 : 8; }
+// padding between the columns of a field, in storage units and in scale floats
+static size_t col_pad_units(int prec) { return kSkew / (prec == PREC_F64 ? 16 : 8); }
+static size_t col_pad_scales() { return kSkew / sizeof(float); }
 static int spinor_nu(int prec) { return prec == PREC_F16 ? 6 : 12; }
 static int clover_nu(int prec) { return prec == PREC_F16 ? 18 : 36; }
 static int link_nu(int prec, int recon) { return (recon == 18 ? 9 : 6) / (prec == PREC_F16 ? 2 : 1); }
@@ -169,6 +182,17 @@ static Geom make_geom(const int* d)
     g.inv_Lxh = 1.0f / (float)g.Lxh;
     g.inv_Ly = 1.0f / (float)d[1];
     g.inv_Lz = 1.0f / (float)d[2];
+    g.ntiles = pad_sites(g.Vh) / kTile;
+    const int plane = g.Lxh * d[1];
+    g.zb = d[2] % 4 == 0 ? 4 : (d[2] % 2 == 0 ? 2 : 1);
+    g.tb = d[3] % 4 == 0 ? 4 : (d[3] % 2 == 0 ? 2 : 1);
+    g.blocked = plane % kTile == 0 && (g.zb > 1 || g.tb > 1);
+    g.nu = g.blocked ? plane / kTile : 1;
+    g.nzb = d[2] / g.zb;
+    g.inv_nu = 1.0f / (float)g.nu;
+    g.inv_zb = 1.0f / (float)g.zb;
+    g.inv_tb = 1.0f / (float)g.tb;
+    g.inv_nzb = 1.0f / (float)g.nzb;
     return g;
 }
 
@@ -230,6 +254,8 @@ struct bq_field_s {
     int nh = 2;
     size_t half_units = 0;  // storage units per parity half per column
     size_t half_sites = 0;  // padded sites per half
+    size_t cstride = 0;     // storage units between columns
+    size_t sstride = 0;     // scale floats between columns (FP16)
     DevBuf data, scale;
 };
 
@@ -260,8 +286,8 @@ static Vec field_vec(bq_field f, int first_half, int nh)
     v.nh = nh;
     v.half_units = f->half_units;
     v.half_sites = f->half_sites;
-    v.cstride = f->half_units * f->nh;
-    v.sstride = f->half_sites * f->nh;
+    v.cstride = f->cstride;
+    v.sstride = f->sstride;
     v.d = (char*)f->data.p + (size_t)first_half * f->half_units * unit_bytes(f->prec);
     v.s = f->prec == PREC_F16 ? f->scale.as<float>() + (size_t)first_half * f->half_sites : nullptr;
     return v;
@@ -276,8 +302,8 @@ static int alloc_vec(bq_context ctx, const Geom& g, int prec, int nh, int ncol, 
     v.nh = nh;
     v.half_sites = pad_sites(g.Vh);
     v.half_units = v.half_sites * spinor_nu(prec);
-    v.cstride = v.half_units * nh;
-    v.sstride = v.half_sites * nh;
+    v.cstride = v.half_units * nh + col_pad_units(prec);
+    v.sstride = v.half_sites * nh + col_pad_scales();
     CHK(data.alloc(ctx, v.cstride * ncol * unit_bytes(prec)));
     v.d = data.p;
     v.s = nullptr;
@@ -300,7 +326,7 @@ static Tune get_tune(bq_context ctx, int prec, int ncol)
     if (it != ctx->tune.end()) return it->second;
     Tune t;
     t.recon = prec == PREC_F16 ? 12 : 18;
-    t.bs = 256;
+    t.bs = ncol > 1 ? 128 : 256;
     t.R = 1;
     for (int r = std::min(max_R(prec), ncol); r >= 1; r--)
         if (ncol % r == 0) {
@@ -958,7 +984,7 @@ int bq_gauge_upload(bq_context ctx, const int dims[4], const double* links, int 
         LinkSet& ls = G->links[f];
         ls.prec = forms[f][0];
         ls.recon = forms[f][1];
-        const size_t per = Vp * link_nu(ls.prec, ls.recon) * unit_bytes(ls.prec);
+        const size_t per = Vp * link_nu(ls.prec, ls.recon) * unit_bytes(ls.prec) + kSkew;
         CHK(ls.buf.alloc(ctx, per * 8));
         for (int k = 0; k < 8; k++) ls.U[k] = (char*)ls.buf.p + per * k;
         for (int p = 0; p < 2; p++) {
@@ -1080,8 +1106,10 @@ int bq_field_create(bq_context ctx, const int dims[4], int subset, int prec, int
     f->nh = subset == BQ_FULL ? 2 : 1;
     f->half_sites = pad_sites(f->g.Vh);
     f->half_units = f->half_sites * spinor_nu(prec);
-    CHK(f->data.alloc(ctx, f->half_units * f->nh * nrhs * unit_bytes(prec)));
-    if (prec == BQ_F16) CHK(f->scale.alloc(ctx, f->half_sites * f->nh * nrhs * sizeof(float)));
+    f->cstride = f->half_units * f->nh + col_pad_units(prec);
+    f->sstride = f->half_sites * f->nh + col_pad_scales();
+    CHK(f->data.alloc(ctx, f->cstride * nrhs * unit_bytes(prec)));
+    if (prec == BQ_F16) CHK(f->scale.alloc(ctx, f->sstride * nrhs * sizeof(float)));
     *out = f.release();
     return BQ_OK;
 }

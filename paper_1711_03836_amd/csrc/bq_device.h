@@ -109,6 +109,71 @@ struct P16 {
 __device__ __forceinline__ float h2f(uint32_t bits16) { return __half2float(__ushort_as_half((unsigned short)bits16)); }
 __device__ __forceinline__ uint32_t f2h(float f) { return (uint32_t)__half_as_ushort(__float2half_rn(f)); }
 
+// Streaming accesses: links and clover are read once per launch and outputs written once;
+// non-temporal loads/stores keep them from evicting the neighbour spinors that the stencil
+// re-reads from L2.  BQ_STREAMING_HINTS=0 turns the hints off.
+#ifndef BQ_STREAMING_HINTS
+#define BQ_STREAMING_HINTS 1
+#endif
+typedef double bq_d2v __attribute__((ext_vector_type(2)));
+typedef float bq_f2v __attribute__((ext_vector_type(2)));
+typedef unsigned bq_u2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld_stream(const double2* p)
+{
+#if BQ_STREAMING_HINTS
+    const bq_d2v t = __builtin_nontemporal_load((const bq_d2v*)p);
+    return make_double2(t.x, t.y);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p)
+{
+#if BQ_STREAMING_HINTS
+    const bq_f2v t = __builtin_nontemporal_load((const bq_f2v*)p);
+    return make_float2(t.x, t.y);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ uint2 ld_stream(const uint2* p)
+{
+#if BQ_STREAMING_HINTS
+    const bq_u2v t = __builtin_nontemporal_load((const bq_u2v*)p);
+    return make_uint2(t.x, t.y);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ void st_stream(double2* p, double2 v)
+{
+#if BQ_STREAMING_HINTS
+    bq_d2v t = {v.x, v.y};
+    __builtin_nontemporal_store(t, (bq_d2v*)p);
+#else
+    *p = v;
+#endif
+}
+__device__ __forceinline__ void st_stream(float2* p, float2 v)
+{
+#if BQ_STREAMING_HINTS
+    bq_f2v t = {v.x, v.y};
+    __builtin_nontemporal_store(t, (bq_f2v*)p);
+#else
+    *p = v;
+#endif
+}
+__device__ __forceinline__ void st_stream(uint2* p, uint2 v)
+{
+#if BQ_STREAMING_HINTS
+    bq_u2v t = {v.x, v.y};
+    __builtin_nontemporal_store(t, (bq_u2v*)p);
+#else
+    *p = v;
+#endif
+}
+
 template <class P, int N> struct CxIO;
 
 template <int N> struct CxIO<P64, N> {
@@ -128,6 +193,16 @@ template <int N> struct CxIO<P64, N> {
 #pragma unroll
         for (int c = 0; c < N; c++) b[toff(j, c, N)] = make_double2(v[c].re, v[c].im);
     }
+    __device__ __forceinline__ static void load_stream(const double2* __restrict__ b, int j, cx<double> (&v)[N])
+    {
+#pragma unroll
+        for (int c = 0; c < N; c++) { double2 t = ld_stream(&b[toff(j, c, N)]); v[c] = {t.x, t.y}; }
+    }
+    __device__ __forceinline__ static void store_stream(double2* __restrict__ b, int j, const cx<double> (&v)[N])
+    {
+#pragma unroll
+        for (int c = 0; c < N; c++) st_stream(&b[toff(j, c, N)], make_double2(v[c].re, v[c].im));
+    }
 };
 
 template <int N> struct CxIO<P32, N> {
@@ -146,6 +221,16 @@ template <int N> struct CxIO<P32, N> {
     {
 #pragma unroll
         for (int c = 0; c < N; c++) b[toff(j, c, N)] = make_float2(v[c].re, v[c].im);
+    }
+    __device__ __forceinline__ static void load_stream(const float2* __restrict__ b, int j, cx<float> (&v)[N])
+    {
+#pragma unroll
+        for (int c = 0; c < N; c++) { float2 t = ld_stream(&b[toff(j, c, N)]); v[c] = {t.x, t.y}; }
+    }
+    __device__ __forceinline__ static void store_stream(float2* __restrict__ b, int j, const cx<float> (&v)[N])
+    {
+#pragma unroll
+        for (int c = 0; c < N; c++) st_stream(&b[toff(j, c, N)], make_float2(v[c].re, v[c].im));
     }
 };
 
@@ -176,6 +261,16 @@ template <int N> struct CxIO<P16, N> {
 #pragma unroll
         for (int c = 0; c < N / 2; c++) b[toff(j, c, N / 2)] = pack(v[2 * c], v[2 * c + 1]);
     }
+    __device__ __forceinline__ static void load_stream(const uint2* __restrict__ b, int j, cx<float> (&v)[N])
+    {
+#pragma unroll
+        for (int c = 0; c < N / 2; c++) unpack(ld_stream(&b[toff(j, c, N / 2)]), v[2 * c], v[2 * c + 1]);
+    }
+    __device__ __forceinline__ static void store_stream(uint2* __restrict__ b, int j, const cx<float> (&v)[N])
+    {
+#pragma unroll
+        for (int c = 0; c < N / 2; c++) st_stream(&b[toff(j, c, N / 2)], pack(v[2 * c], v[2 * c + 1]));
+    }
 };
 
 // Units of storage for one site of each object.
@@ -203,7 +298,7 @@ __device__ __forceinline__ void load_spinor(const SpinorPtr<P>& f, int col, int 
     }
 }
 
-template <class P>
+template <class P, bool STREAM = false>
 __device__ __forceinline__ void store_spinor(const SpinorPtr<P>& f, int col, int j, cx<typename P::real> (&v)[12])
 {
     if constexpr (P::id == PREC_F16) {
@@ -214,8 +309,14 @@ __device__ __forceinline__ void store_spinor(const SpinorPtr<P>& f, int col, int
         cx<float> w[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) w[k] = cscale(inv, v[k]);
-        CxIO<P, 12>::store(f.d + col * f.cstride, j, w);
+        if constexpr (STREAM) {
+            CxIO<P, 12>::store_stream(f.d + col * f.cstride, j, w);
+        } else {
+            CxIO<P, 12>::store(f.d + col * f.cstride, j, w);
+        }
         f.s[col * f.sstride + j] = m;
+    } else if constexpr (STREAM) {
+        CxIO<P, 12>::store_stream(f.d + col * f.cstride, j, v);
     } else {
         CxIO<P, 12>::store(f.d + col * f.cstride, j, v);
     }
@@ -231,6 +332,12 @@ struct Geom {
     int Vh;       // sites per parity
     int sy, sz, st;        // checkerboard-index strides of a y, z, t step
     float inv_Lxh, inv_Ly, inv_Lz;
+    // Traversal order of the 64-site tiles by stencil kernels: when an (x,y) plane of a
+    // checkerboard holds a whole number `nu` of tiles, tiles are visited plane by plane in
+    // blocks of zb x tb (z,t) planes, so that the +-t and +-z neighbours of the planes in
+    // flight are a few planes away instead of a whole time slice.  ntiles = tiles per parity.
+    int ntiles, blocked, nu, zb, tb, nzb;
+    float inv_nu, inv_zb, inv_tb, inv_nzb;
 };
 
 // exact quotient/remainder of n < 2^24 by d using a float reciprocal and one correction
@@ -240,6 +347,21 @@ __device__ __forceinline__ int fdiv(int n, int d, float inv)
     int r = n - q * d;
     q += (r >= d) - (r < 0);
     return q;
+}
+
+// physical tile visited at logical position `lt` (see Geom)
+__device__ __forceinline__ int tile_at(const Geom& g, int lt)
+{
+    if (!g.blocked) return lt;
+    const int r1 = fdiv(lt, g.nu, g.inv_nu);
+    const int u = lt - r1 * g.nu;
+    const int r2 = fdiv(r1, g.zb, g.inv_zb);
+    const int zl = r1 - r2 * g.zb;
+    const int r3 = fdiv(r2, g.tb, g.inv_tb);
+    const int tl = r2 - r3 * g.tb;
+    const int ti = fdiv(r3, g.nzb, g.inv_nzb);
+    const int zi = r3 - ti * g.nzb;
+    return u + g.nu * ((zi * g.zb + zl) + g.L[2] * (ti * g.tb + tl));
 }
 
 struct Site {

@@ -10,6 +10,8 @@
 // by the caller, so that an operator application never writes the raw hop.
 #pragma once
 
+#include <algorithm>
+
 #include "bq_kernels.h"
 
 namespace bq {
@@ -78,10 +80,10 @@ __device__ __forceinline__ void load_link(const typename P::unit* __restrict__ U
 {
     using T = typename P::real;
     if constexpr (RECON == 18) {
-        CxIO<P, 9>::load_cached(U, j, u);
+        CxIO<P, 9>::load_stream(U, j, u);
     } else {
         cx<T> r[6];
-        CxIO<P, 6>::load_cached(U, j, r);
+        CxIO<P, 6>::load_stream(U, j, r);
 #pragma unroll
         for (int k = 0; k < 6; k++) u[k] = r[k];
         // third row of an SU(3) matrix: conj(row0 x row1)
@@ -136,11 +138,11 @@ __device__ __forceinline__ void load_clover_block(const typename P::unit* __rest
 {
     if constexpr (P::id == PREC_F16) {
 #pragma unroll
-        for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(C[toff(j, blk * 9 + u, 18)], c[2 * u], c[2 * u + 1]);
+        for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(ld_stream(&C[toff(j, blk * 9 + u, 18)]), c[2 * u], c[2 * u + 1]);
     } else {
 #pragma unroll
         for (int k = 0; k < 18; k++) {
-            auto t = C[toff(j, blk * 18 + k, 36)];
+            auto t = ld_stream(&C[toff(j, blk * 18 + k, 36)]);
             c[k] = {t.x, t.y};
         }
     }
@@ -201,6 +203,8 @@ struct Args {
     const double* alpha;
     double* partial;
     int nwaves, pstride;
+    int tpb, gw, nch;  // tiles per workgroup, column groups per workgroup, group chunks
+    int nblk;          // tile blocks
     const int* status;
     int statmask;
     typename P::real ef, eb, ef_bc, eb_bc;  // time coefficients, without / with the boundary sign
@@ -272,18 +276,21 @@ __device__ __forceinline__ void hop_dir(const Args<P, PR>& A, const Site& s, con
     phase_end(act, acc);
 }
 
+// One work item: tile block `tblk` (tpb tiles) x column-group chunk `chunk` (gw groups of R
+// columns).  Wave w of the workgroup handles tile w / gw and group w % gw, so all groups of a
+// tile run side by side and share the links and clover through L1/L2.
 template <class P, class PR, int R, int DAG, int EPI, int RECON>
-__global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
+__device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chunk)
 {
     using T = typename P::real;
     using TR = typename PR::real;
-    const int ngroups = (A.ncol + R - 1) / R;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int sb = lb / ngroups;
-    const int grp = lb - sb * ngroups;
-    const int j = sb * blockDim.x + threadIdx.x;
+    const int w = threadIdx.x >> kTileLog;
+    const int lane = threadIdx.x & (kTile - 1);
+    const int gl = w % A.gw;
+    const int lt = tblk * A.tpb + w / A.gw;
+    const int grp = chunk * A.gw + gl;
+    const int j = lt < A.g.ntiles ? tile_at(A.g, lt) * kTile + lane : A.g.ntiles * kTile;
     const int c0 = grp * R;
-
     bool act[R];
     bool any = false;
 #pragma unroll
@@ -342,7 +349,7 @@ __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
             }
 #pragma unroll
             for (int r = 0; r < R; r++)
-                if (act[r]) store_spinor(A.out, c0 + r, j, acc[r]);
+                if (act[r]) store_spinor<P, true>(A.out, c0 + r, j, acc[r]);
         } else if constexpr (EPI == EPI_TV) {
             // out = C v + f*hop, assembled in place (FP16 storage needs the whole site for its scale)
 #pragma unroll
@@ -393,7 +400,7 @@ __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
                         const cx<T> w = caxpy(A.f, acc[r][blk * 6 + k], y[k]);
                         rv[k].re = fmadd(-al, (TR)w.re, rv[k].re);
                         rv[k].im = fmadd(-al, (TR)w.im, rv[k].im);
-                        rb[toff(j, blk * 6 + k, 12)] = {rv[k].re, rv[k].im};
+                        st_stream(&rb[toff(j, blk * 6 + k, 12)], {rv[k].re, rv[k].im});
                         n += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
                     }
                     nrm[r] += n;
@@ -415,6 +422,16 @@ __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
             }
         }
     }
+}
+
+
+// One work item per workgroup; blocks are mapped XCD-contiguously (see xcd_remap).
+template <class P, class PR, int R, int DAG, int EPI, int RECON>
+__global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
+{
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int tblk = lb / A.nch;
+    hop_item<P, PR, R, DAG, EPI, RECON>(A, tblk, lb - tblk * A.nch);
 }
 
 template <class P>
@@ -450,9 +467,14 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
     A.eb_bc = (T)(L.eb * L.tbc);
     A.f = (T)L.f;
     A.a = (T)L.a;
-    const int nsb = (L.g.Vh + L.bs - 1) / L.bs;
-    const int ngroups = (L.ncol + R - 1) / R;
-    hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON>), dim3(nsb * ngroups), dim3(L.bs), 0, st, A);
+    // L.bs = sites per workgroup (a multiple of 64); at most 512 threads per workgroup
+    const int G = (L.ncol + R - 1) / R;
+    const int tpb = std::max(1, L.bs / kTile);
+    A.tpb = tpb;
+    A.gw = std::max(1, std::min(G, 512 / (tpb * kTile)));
+    A.nch = (G + A.gw - 1) / A.gw;
+    A.nblk = (L.g.ntiles + tpb - 1) / tpb;
+    hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON>), dim3(A.nblk * A.nch), dim3(tpb * kTile * A.gw), 0, st, A);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ struct HopLaunch {
     int dagger = 0;
     int epi = EPI_HOP;
     int R = 1;               // columns per thread
-    int bs = 256;            // threads per block
+    int bs = 256;            // sites per workgroup (a multiple of 64)
     Geom g{};
     int parity = 0;          // output parity
     int ncol = 1;

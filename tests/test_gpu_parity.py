@@ -100,7 +100,7 @@ def test_operator_parity(bq, setup, kind_name, prec):
 @pytest.mark.parametrize("prec,recon,R,bs", [(0, 12, 1, 64), (0, 18, 2, 128), (0, 12, 2, 512), (1, 12, 3, 256),
                                              (1, 18, 4, 64), (1, 12, 1, 512), (2, 12, 2, 128), (2, 12, 4, 256)])
 def test_kernel_configurations(bq, setup, prec, recon, R, bs):
-    """Every link form, column tile and block size gives the oracle's result (12 columns, K1 and Mhat)."""
+    """Every link form, column tile and workgroup shape gives the oracle's result (12 columns, K1 and Mhat)."""
     ctx, G, op, ref, U = setup
     nrhs = 12
     ctx.tune_set(prec, nrhs, recon, R, bs)
@@ -281,3 +281,55 @@ def test_hbm_budget(bq):
     with pytest.raises(bq.BqError) as e:
         bq.Field(ctx, (8, 8, 8, 8), bq.BQ_FULL, 0, 4)
     assert e.value.code == bq.BQ_ERR_OOM
+
+
+@pytest.mark.parametrize("dims", [(8, 16, 8, 8), (8, 32, 4, 6)])
+@pytest.mark.parametrize("prec,recon,R,sb", [(0, 18, 2, 64), (1, 12, 3, 128), (2, 12, 4, 64), (1, 12, 1, 256)])
+def test_blocked_traversal_lattices(bq, dims, prec, recon, R, sb):
+    """Lattices whose (x,y) planes hold whole 64-site tiles are visited in (z,t) blocks; results unchanged."""
+    U = inputs.gauge_field(dims, 0.3, seed=17)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.124, 1.5, 0.1)
+    ref = orc.Operator(dims, U, 0.124, 1.5, mu=0.1)
+    nrhs = 12 if R > 1 else 1
+    ctx.tune_set(prec, nrhs, recon, R, sb)
+    psi = inputs.gaussian_spinor(dims, nrhs, seed=23)
+    for kind in (bq.BQ_OP_K1, bq.BQ_OP_MHATDAG_MHAT, bq.BQ_OP_M):
+        si, so = bq.OP_SUBSETS[kind]
+        fi = bq.Field(ctx, dims, si, prec, nrhs)
+        fo = bq.Field(ctx, dims, so, prec, nrhs)
+        fi.put(psi)
+        op.apply(kind, fi, fo)
+        got = fo.get()
+        mask = {bq.BQ_EVEN: ref.parity == 0, bq.BQ_ODD: ref.parity == 1, bq.BQ_FULL: np.ones(ref.V, bool)}[so]
+        for c in sorted({0, nrhs // 2, nrhs - 1}):
+            want = oracle_apply(ref, kind, bq, psi[c])
+            assert maxrel(got[c][mask], want[mask]) < TOL[prec], (kind, c)
+    b = inputs.gaussian_spinor(dims, 2, seed=29)
+    x, info = _solve(bq, op, dims, b, bq.BQ_SYS_M, prec, 1e-10, 2)
+    for c in range(2):
+        assert info[c]["converged"]
+        assert np.linalg.norm(b[c] - ref.M(x[c])) / np.linalg.norm(b[c]) < 1e-7
+
+
+@pytest.mark.parametrize("prec,nrhs,recon,R,sb", [(1, 12, 12, 3, 64), (0, 1, 18, 1, 64), (2, 12, 12, 4, 128)])
+def test_larger_lattice_k1(bq, prec, nrhs, recon, R, sb):
+    """16^3x32 (blocked traversal, 1024 tiles per parity): K1 against the oracle on the whole lattice."""
+    dims = (16, 16, 16, 32)
+    U = inputs.gauge_field(dims, 0.2, seed=41)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.125, 1.7, 0.0)
+    ref = orc.Operator(dims, U, 0.125, 1.7)
+    ctx.tune_set(prec, nrhs, recon, R, sb)
+    psi = inputs.gaussian_spinor(dims, nrhs, seed=43)
+    fi = bq.Field(ctx, dims, bq.BQ_ODD, prec, nrhs)
+    fo = bq.Field(ctx, dims, bq.BQ_EVEN, prec, nrhs)
+    fi.put(psi)
+    op.apply(bq.BQ_OP_K1, fi, fo)
+    got = fo.get()
+    even = ref.parity == 0
+    for c in sorted({0, nrhs - 1}):
+        want = oracle_apply(ref, bq.BQ_OP_K1, bq, psi[c])
+        assert maxrel(got[c][even], want[even]) < TOL[prec]
