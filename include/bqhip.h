@@ -52,6 +52,7 @@ extern "C" {
 #endif
 
 #define BQ_OK 0
+#define BQ_PENDING 1                /* bq_server_result: the request is still queued or running */
 #define BQ_ERR_INVALID (-1)         /* bad argument: NULL, odd or < 2 extent, nrhs < 1, tol <= 0, mismatch */
 #define BQ_ERR_OOM (-2)             /* HBM budget exceeded or device allocation failed */
 #define BQ_ERR_NOT_CONVERGED (-3)   /* maxiter reached; x holds the last iterate, info is filled */
@@ -95,6 +96,7 @@ typedef struct bq_context_s* bq_context;
 typedef struct bq_gauge_s* bq_gauge;
 typedef struct bq_op_s* bq_op;
 typedef struct bq_field_s* bq_field;
+typedef struct bq_server_s* bq_server;
 
 typedef struct {
     double tol;        /* stop when the FP64 true residual |b' - A x| <= tol |b'| (A, b' of the CG system) */
@@ -202,6 +204,32 @@ int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs)
 int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs);
 /* Time the candidate configurations for (op's lattice, prec, nrhs) on op and keep the fastest. */
 int bq_autotune(bq_op op, int prec, int nrhs);
+
+/* ---------------------------------------------------------------------------
+ * Continuous-batching solve server (many requests, mixed lattices and kappa).
+ * Requests M x = b (the BQ_SYS_M system) on resident gauge fields are queued by
+ * bq_server_submit and advanced by bq_server_step: each step admits queued
+ * requests into free column slots of the session of their gauge field (one
+ * session per gauge field, mu and inner precision, `slots` columns each) when
+ * their operator fits in the context's HBM budget, runs one chunk of CG
+ * iterations on every session (sessions overlap on the device), and retires the
+ * requests whose columns have converged.  Columns of one session have their own
+ * kappa and clover and share the link reads; a request gives the same result
+ * alone and batched with others.  Single host thread per server.
+ * ------------------------------------------------------------------------- */
+int bq_server_create(bq_context ctx, int slots, int chunk, bq_server* out);
+/* b: nrhs canonical host spinors; x: host array of the same size that receives the
+ * solutions.  Both are owned by the caller and must stay valid until the request retires. */
+int bq_server_submit(bq_server s, bq_gauge g, double kappa, double csw, double mu, const double* b, double* x,
+                     int nrhs, double tol, int inner_prec, int maxiter, uint64_t* ticket);
+/* One scheduling step; up to max_done tickets completed in this step are written to
+ * done_tickets, *ndone = their number. */
+int bq_server_step(bq_server s, uint64_t* done_tickets, int max_done, int* ndone);
+/* BQ_PENDING while queued or running; afterwards the request's status (info[nrhs]
+ * filled) and the ticket is forgotten. */
+int bq_server_result(bq_server s, uint64_t ticket, bq_solve_info* info);
+int bq_server_pending(bq_server s, int* queued, int* running);
+int bq_server_free(bq_server s);
 
 #ifdef __cplusplus
 }

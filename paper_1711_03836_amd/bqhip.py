@@ -34,6 +34,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 BQ_OK = 0
+BQ_PENDING = 1
 ERRORS = {-1: "BQ_ERR_INVALID", -2: "BQ_ERR_OOM", -3: "BQ_ERR_NOT_CONVERGED", -4: "BQ_ERR_NONFINITE",
           -5: "BQ_ERR_CLOVER_NOT_HPD", -6: "BQ_ERR_BUSY", -7: "BQ_ERR_DEVICE", -8: "BQ_ERR_UNSUPPORTED"}
 BQ_ERR_INVALID, BQ_ERR_OOM, BQ_ERR_NOT_CONVERGED, BQ_ERR_NONFINITE = -1, -2, -3, -4
@@ -105,6 +106,13 @@ _sig = {
     "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
     "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
+    "bq_server_create": (C.c_int, [_h, C.c_int, C.c_int, _P(_h)]),
+    "bq_server_submit": (C.c_int, [_h, _h, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
+                                   C.c_double, C.c_int, C.c_int, _P(C.c_uint64)]),
+    "bq_server_step": (C.c_int, [_h, _P(C.c_uint64), C.c_int, _P(C.c_int)]),
+    "bq_server_result": (C.c_int, [_h, C.c_uint64, _P(bq_solve_info)]),
+    "bq_server_pending": (C.c_int, [_h, _P(C.c_int), _P(C.c_int)]),
+    "bq_server_free": (C.c_int, [_h]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -288,6 +296,59 @@ class Field:
     def close(self):
         if self.h:
             check(bq_field_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server (see bq_server_* in bqhip.h)."""
+
+    def __init__(self, ctx: Context, slots=16, chunk=16):
+        self.ctx = ctx
+        h = _h()
+        check(bq_server_create(ctx.h, int(slots), int(chunk), C.byref(h)))
+        self.h = h
+        self._keep = {}  # ticket -> (gauge, b, x): kept alive until retirement
+
+    def submit(self, gauge: Gauge, b, kappa, csw, mu=0.0, tol=1e-10, inner_prec=BQ_F32, maxiter=100000):
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        x = np.zeros_like(b)
+        t = C.c_uint64()
+        check(bq_server_submit(self.h, gauge.h, float(kappa), float(csw), float(mu), b.ctypes.data_as(C.c_void_p),
+                               x.ctypes.data_as(C.c_void_p), b.shape[0], float(tol), int(inner_prec), int(maxiter),
+                               C.byref(t)))
+        self._keep[t.value] = (gauge, b, x)
+        return t.value
+
+    def step(self, max_done=4096):
+        done = (C.c_uint64 * max_done)()
+        n = C.c_int()
+        check(bq_server_step(self.h, done, max_done, C.byref(n)))
+        return [done[i] for i in range(min(n.value, max_done))]
+
+    def result(self, ticket):
+        """(rc, info list, x) once retired; None while pending."""
+        g, b, x = self._keep[ticket]
+        info = (bq_solve_info * b.shape[0])()
+        rc = bq_server_result(self.h, C.c_uint64(ticket), info)
+        if rc == BQ_PENDING:
+            return None
+        del self._keep[ticket]
+        return rc, [i.as_dict() for i in info], x
+
+    def pending(self):
+        q, r = C.c_int(), C.c_int()
+        check(bq_server_pending(self.h, C.byref(q), C.byref(r)))
+        return q.value, r.value
+
+    def close(self):
+        if self.h:
+            check(bq_server_free(self.h))
             self.h = None
 
     def __del__(self):

@@ -226,6 +226,7 @@ struct bq_gauge_s {
     int t_bc = -1;
     int nops = 0;
     LinkSet links[5];  // F64/18, F64/12, F32/18, F32/12, F16/12
+    DevBuf B[2];       // kappa-independent clover field sum sigma (x) F per parity (built on first use)
     const LinkSet* get(int prec, int recon) const
     {
         for (const auto& l : links)
@@ -375,6 +376,16 @@ static int run_hop(const HopLaunch& L, hipStream_t st)
 // operator building blocks on views (precision of the views = prec)
 // ---------------------------------------------------------------------------
 
+// Per-column operators: column c of a batch uses the clover blocks and kappa of its own
+// request (same gauge field and mu).  Pointers per precision and parity.
+struct ColTable {
+    const void* T[3][2][kMaxCols];
+    const void* Tinv[3][2][kMaxCols];
+    double kappa[kMaxCols];
+};
+// how a stencil launch scales the hop per column when a ColTable is given
+enum { FK_CONST = -1, FK_KAPPA = 0, FK_MKAPPA = 1, FK_MKAPPA2 = 2 };
+
 struct OpCall {
     bq_op op;
     int prec;
@@ -383,11 +394,30 @@ struct OpCall {
     const int* status = nullptr;
     int statmask = 1;
     hipStream_t st;
+    const ColTable* ct = nullptr;
 };
+
+// switch a launch to per-column operators: clover per column (parity `par`, inverse or not), f by mode
+static void apply_cols(const OpCall& c, HopLaunch& L, int par, bool inverse, int fk)
+{
+    if (!c.ct) return;
+    L.percol = 1;
+    if (L.recon != 12) {
+        L.recon = 12;
+        const LinkSet* ls = c.op->gauge->get(c.prec, 12);
+        for (int k = 0; k < 8; k++) L.U[k] = ls ? ls->U[k] : nullptr;
+    }
+    if (c.prec == PREC_F64) L.R = 1;  // FP64 per-column variants spill above one column per thread
+    for (int col = 0; col < c.ncol && col < kMaxCols; col++) {
+        L.cclov[col] = inverse ? c.ct->Tinv[c.prec][par][col] : c.ct->T[c.prec][par][col];
+        const double k = c.ct->kappa[col];
+        L.cf[col] = fk == FK_KAPPA ? k : (fk == FK_MKAPPA ? -k : (fk == FK_MKAPPA2 ? -k * k : L.f));
+    }
+}
 
 // K1: out_e = T_ee^-1 (a v_e + f D_eo in_o)   (or with D^dag)
 static int k1(const OpCall& c, int dag, FieldArg in_o, FieldArg out_e, FieldArg v_e = FieldArg(), double a = 0,
-              double f = 1)
+              double f = 1, int fk = FK_CONST)
 {
     HopLaunch L = hop_base(c.op, c.prec, c.t, dag, 0, c.ncol);
     L.epi = EPI_TINV;
@@ -399,12 +429,13 @@ static int k1(const OpCall& c, int dag, FieldArg in_o, FieldArg out_e, FieldArg 
     L.clov = c.op->Tinv[c.prec][0].p;
     L.status = c.status;
     L.statmask = c.statmask;
+    apply_cols(c, L, 0, true, fk);
     return run_hop(L, c.st);
 }
 
 // out_p = C_p v_p + f D_{p,1-p} in    (+ |out|^2 partials)
 static int tv(const OpCall& c, int dag, int parity, FieldArg in, FieldArg v, FieldArg out, double f, double* partial,
-              int nwaves, int pstride)
+              int nwaves, int pstride, int fk = FK_CONST)
 {
     HopLaunch L = hop_base(c.op, c.prec, c.t, dag, parity, c.ncol);
     L.epi = EPI_TV;
@@ -418,12 +449,13 @@ static int tv(const OpCall& c, int dag, int parity, FieldArg in, FieldArg v, Fie
     L.pstride = pstride;
     L.status = c.status;
     L.statmask = c.statmask;
+    apply_cols(c, L, parity, false, fk);
     return run_hop(L, c.st);
 }
 
 // r_out = r_in - alpha (C_p v_p + f D_{p,1-p} in)   (+ |r_out|^2 partials)
 static int tvr(const OpCall& c, int dag, int parity, FieldArg in, FieldArg v, FieldArg rin, FieldArg rout, double f,
-               const double* alpha, double* partial, int nwaves, int pstride)
+               const double* alpha, double* partial, int nwaves, int pstride, int fk = FK_CONST)
 {
     HopLaunch L = hop_base(c.op, c.prec, c.t, dag, parity, c.ncol);
     L.epi = EPI_TVR;
@@ -439,11 +471,13 @@ static int tvr(const OpCall& c, int dag, int parity, FieldArg in, FieldArg v, Fi
     L.pstride = pstride;
     L.status = c.status;
     L.statmask = c.statmask;
+    apply_cols(c, L, parity, false, fk);
     return run_hop(L, c.st);
 }
 
 // out_p = a v_p + f D_{p,1-p} in
-static int hopv(const OpCall& c, int dag, int parity, FieldArg in, FieldArg out, FieldArg v, double a, double f)
+static int hopv(const OpCall& c, int dag, int parity, FieldArg in, FieldArg out, FieldArg v, double a, double f,
+                int fk = FK_CONST)
 {
     HopLaunch L = hop_base(c.op, c.prec, c.t, dag, parity, c.ncol);
     L.epi = EPI_HOP;
@@ -454,6 +488,7 @@ static int hopv(const OpCall& c, int dag, int parity, FieldArg in, FieldArg out,
     L.f = f;
     L.status = c.status;
     L.statmask = c.statmask;
+    apply_cols(c, L, parity, false, fk);
     return run_hop(L, c.st);
 }
 
@@ -464,7 +499,7 @@ static int op_fwd(const OpCall& c, int full, const Vec& p, const Vec& q, const V
     const double k = c.op->kappa;
     if (!full) {
         CHK(k1(c, 0, p.half(0), t.half(0)));
-        return tv(c, 0, 1, t.half(0), p.half(0), q.half(0), -k * k, partial, hw, hw);
+        return tv(c, 0, 1, t.half(0), p.half(0), q.half(0), -k * k, partial, hw, hw, c.ct ? FK_MKAPPA2 : FK_CONST);
     }
     CHK(tv(c, 0, 0, p.half(1), p.half(0), q.half(0), -k, partial, hw, 2 * hw));
     return tv(c, 0, 1, p.half(0), p.half(1), q.half(1), -k, partial ? partial + hw : nullptr, hw, 2 * hw);
@@ -477,7 +512,8 @@ static int op_dag_r(const OpCall& c, int full, const Vec& q, const Vec& t, const
     const double k = c.op->kappa;
     if (!full) {
         CHK(k1(c, 1, q.half(0), t.half(0)));
-        return tvr(c, 1, 1, t.half(0), q.half(0), rin.half(0), rout.half(0), -k * k, alpha, partial, hw, hw);
+        return tvr(c, 1, 1, t.half(0), q.half(0), rin.half(0), rout.half(0), -k * k, alpha, partial, hw, hw,
+                   c.ct ? FK_MKAPPA2 : FK_CONST);
     }
     CHK(tvr(c, 1, 0, q.half(1), q.half(0), rin.half(0), rout.half(0), -k, alpha, partial, hw, 2 * hw));
     return tvr(c, 1, 1, q.half(0), q.half(1), rin.half(1), rout.half(1), -k, alpha, partial ? partial + hw : nullptr,
@@ -507,6 +543,7 @@ struct Workspace {
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     double graph_delta2 = -1;
+    const ColTable* ct = nullptr;  // per-column operators (server sessions)
     ~Workspace()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -517,18 +554,8 @@ struct Workspace {
 
 bq_op_s::~bq_op_s() = default;
 
-static int ws_get(bq_op op, int ncol, int prec, int full, Workspace** out)
+static int ws_init(bq_context ctx, const Geom& g, int ncol, int prec, int full, Workspace* w)
 {
-    Workspace* w = op->ws.get();
-    if (w && w->ncol == ncol && w->prec == prec && w->full == full) {
-        *out = w;
-        return BQ_OK;
-    }
-    op->ws.reset();
-    auto nw = std::make_unique<Workspace>();
-    w = nw.get();
-    bq_context ctx = op->gauge->ctx;
-    const Geom& g = op->gauge->g;
     const int nh = full ? 2 : 1;
     w->ncol = ncol;
     w->prec = prec;
@@ -557,21 +584,33 @@ static int ws_get(bq_op op, int ncol, int prec, int full, Workspace** out)
     w->partial = w->part.as<double>();
     CHK(w->scal.alloc(ctx, sizeof(double) * (size_t)ncol * 10));
     CHK(w->ints.alloc(ctx, sizeof(int) * (size_t)ncol * 4));
-    double* s = w->scal.as<double>();
+    double* sc = w->scal.as<double>();
     int* i = w->ints.as<int>();
-    w->cs.rho = s;
-    w->cs.pAp = s + ncol;
-    w->cs.alpha = s + 2 * ncol;
-    w->cs.beta = s + 3 * ncol;
-    w->cs.stop2 = s + 4 * ncol;
-    w->cs.rmax2 = s + 5 * ncol;
-    w->dtmp = s + 6 * ncol;  // 4 * ncol
+    w->cs.rho = sc;
+    w->cs.pAp = sc + ncol;
+    w->cs.alpha = sc + 2 * ncol;
+    w->cs.beta = sc + 3 * ncol;
+    w->cs.stop2 = sc + 4 * ncol;
+    w->cs.rmax2 = sc + 5 * ncol;
+    w->dtmp = sc + 6 * ncol;  // 4 * ncol
     w->cs.status = i;
     w->cs.iters = i + ncol;
     w->cs.restart = i + 2 * ncol;
     w->cs.nrel = i + 3 * ncol;
     HIPCHK(hipHostMalloc((void**)&w->h_status, sizeof(int) * ncol * 4));
-    w->h_iters = nullptr;
+    return BQ_OK;
+}
+
+static int ws_get(bq_op op, int ncol, int prec, int full, Workspace** out)
+{
+    Workspace* w = op->ws.get();
+    if (w && w->ncol == ncol && w->prec == prec && w->full == full) {
+        *out = w;
+        return BQ_OK;
+    }
+    op->ws.reset();
+    auto nw = std::make_unique<Workspace>();
+    CHK(ws_init(op->gauge->ctx, op->gauge->g, ncol, prec, full, nw.get()));
     op->ws = std::move(nw);
     *out = op->ws.get();
     return BQ_OK;
@@ -637,6 +676,7 @@ static int cg_iteration(bq_op op, Workspace* w, int prec, hipStream_t st)
     bq_context ctx = op->gauge->ctx;
     const int n = w->xs.sites();
     OpCall c{op, prec, get_tune(ctx, prec, w->ncol), w->ncol, w->cs.status, kIterMask, st};
+    c.ct = w->ct;
     CHK(op_fwd(c, w->full, w->ps, w->qs, w->ts, w->partial, w->hw));
     HIPCHK(launch_fin_alpha(w->cs, w->partial, w->pstride, w->ncol, st));
     CHK(op_dag_r(c, w->full, w->qs, w->ts, w->rs, w->rs, w->cs.alpha, w->partial, w->hw));
@@ -652,6 +692,7 @@ static int true_residual(bq_op op, Workspace* w, const int* status, int statmask
 {
     bq_context ctx = op->gauge->ctx;
     OpCall c{op, PREC_F64, get_tune(ctx, PREC_F64, w->ncol), w->ncol, status, statmask, st};
+    c.ct = w->ct;
     CHK(op_fwd(c, w->full, w->x, w->q64, w->t64, nullptr, w->hw));
     return op_dag_r(c, w->full, w->q64, w->t64, w->bp, w->r, nullptr, w->partial, w->hw);
 }
@@ -1027,7 +1068,14 @@ int bq_gauge_free(bq_gauge g)
     return BQ_OK;
 }
 
-int bq_op_create(bq_gauge g, double kappa, double csw, double mu, bq_op* out)
+}  // extern "C"
+
+// Operator construction.  The gauge field keeps B = sum_{mu<nu} sigma_{mu nu} (x) F_{mu nu}
+// (independent of kappa and c_SW), built once from the links; an operator then needs only
+// T = 1 + kappa c_SW B and the Cholesky inverse of its blocks.
+// lean_prec >= 0 builds only what a solve in that inner precision needs: FP64 T on both
+// parities and T_ee^-1, plus T_oo and T_ee^-1 in lean_prec.
+static int op_build(bq_gauge g, double kappa, double csw, double mu, int lean_prec, bq_op* out)
 {
     if (!g || !out) return fail(BQ_ERR_INVALID, "NULL argument");
     *out = nullptr;
@@ -1035,47 +1083,61 @@ int bq_op_create(bq_gauge g, double kappa, double csw, double mu, bq_op* out)
         return fail(BQ_ERR_INVALID, "kappa, c_SW and mu must be finite");
     bq_context ctx = g->ctx;
     HIPCHK(hipSetDevice(ctx->device));
+    const size_t Vp = pad_sites(g->g.Vh);
+    if (!g->B[0].p) {
+        for (int p = 0; p < 2; p++) CHK(g->B[p].alloc(ctx, Vp * 36 * 16));
+        CloverBuild cb;
+        cb.g = g->g;
+        const LinkSet* ls = g->get(PREC_F64, 18);
+        for (int k = 0; k < 8; k++) cb.U64[k] = (const double2*)ls->U[k];
+        for (int p = 0; p < 2; p++) cb.B[p] = g->B[p].as<double2>();
+        HIPCHK(launch_clover_build(cb, ctx->stream));
+    }
     auto op = std::make_unique<bq_op_s>();
     op->gauge = g;
     op->kappa = kappa;
     op->csw = csw;
     op->mu = mu;
-    const size_t Vp = pad_sites(g->g.Vh);
-    for (int p = 0; p < 2; p++) {
-        CHK(op->T[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
-        CHK(op->Tinv[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
-    }
     DevBuf bad;
     CHK(bad.alloc(ctx, sizeof(int)));
-    CloverBuild cb;
-    cb.g = g->g;
-    const LinkSet* ls = g->get(PREC_F64, 18);
-    for (int k = 0; k < 8; k++) cb.U64[k] = (const double2*)ls->U[k];
-    cb.ckappa = kappa * csw;
     for (int p = 0; p < 2; p++) {
-        cb.T[p] = op->T[PREC_F64][p].as<double2>();
-        cb.Tinv[p] = op->Tinv[PREC_F64][p].as<double2>();
+        CHK(op->T[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
+        const bool inv = lean_prec < 0 || p == 0;
+        if (inv) CHK(op->Tinv[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
+        HIPCHK(launch_clover_from_B(g->g, p, g->B[p].as<double2>(), kappa * csw, op->T[PREC_F64][p].as<double2>(),
+                                    inv ? op->Tinv[PREC_F64][p].as<double2>() : nullptr, bad.as<int>(), ctx->stream));
     }
-    cb.bad = bad.as<int>();
-    HIPCHK(launch_clover_build(cb, ctx->stream));
     int hbad = 0;
     HIPCHK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (hbad) return fail(BQ_ERR_CLOVER_NOT_HPD, "clover block not positive definite (kappa*c_SW = %g)", kappa * csw);
     for (int prec : {PREC_F32, PREC_F16}) {
+        if (lean_prec >= 0 && prec != lean_prec) continue;
         const size_t bytes = Vp * clover_nu(prec) * unit_bytes(prec);
         for (int p = 0; p < 2; p++) {
-            CHK(op->T[prec][p].alloc(ctx, bytes));
-            CHK(op->Tinv[prec][p].alloc(ctx, bytes));
-            HIPCHK(launch_clover_convert(prec, op->T[PREC_F64][p].as<double2>(), op->T[prec][p].p, g->g.Vh, ctx->stream));
-            HIPCHK(launch_clover_convert(prec, op->Tinv[PREC_F64][p].as<double2>(), op->Tinv[prec][p].p, g->g.Vh,
-                                         ctx->stream));
+            if (lean_prec < 0 || p == 1) {
+                CHK(op->T[prec][p].alloc(ctx, bytes));
+                HIPCHK(launch_clover_convert(prec, op->T[PREC_F64][p].as<double2>(), op->T[prec][p].p, g->g.Vh,
+                                             ctx->stream));
+            }
+            if (lean_prec < 0 || p == 0) {
+                CHK(op->Tinv[prec][p].alloc(ctx, bytes));
+                HIPCHK(launch_clover_convert(prec, op->Tinv[PREC_F64][p].as<double2>(), op->Tinv[prec][p].p, g->g.Vh,
+                                             ctx->stream));
+            }
         }
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     g->nops++;
     *out = op.release();
     return BQ_OK;
+}
+
+extern "C" {
+
+int bq_op_create(bq_gauge g, double kappa, double csw, double mu, bq_op* out)
+{
+    return op_build(g, kappa, csw, mu, -1, out);
 }
 
 int bq_op_free(bq_op op)
@@ -1526,6 +1588,414 @@ int bq_autotune(bq_op op, int prec, int nrhs)
         return fail(BQ_ERR_DEVICE, "no kernel configuration could be timed");
     }
     ctx->tune[{prec, nrhs}] = bt;
+    return BQ_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// continuous-batching server
+//
+// One session per (gauge field, mu, inner precision): a multi-column CG workspace of `cap`
+// column slots on its own stream.  Each step
+//   1. admits queued requests whose columns fit in free slots and whose operator fits in
+//      the HBM budget: the operator (clover for the request's kappa) is built from the
+//      gauge field's kappa-independent B, the source is copied into the slots and prepared
+//      (bhat, b' = Mhat^dag bhat) on the device for the new columns only;
+//   2. runs one chunk of CG iterations plus a reliable-update pass on every session, all
+//      sessions launched before any is waited on, so that their work overlaps on the GPU;
+//   3. retires requests whose columns are done: reconstruction of the even sites, FP64
+//      residual check, copy-out, slots and operator freed.
+// Columns of one batch have their own kappa and clover (per-column stencil launches) and
+// share the links.  A column's arithmetic does not depend on the other columns, and it
+// enters at a chunk boundary, so its result is the same alone and in the mix.
+// ---------------------------------------------------------------------------
+
+static const int COL_NEW = 5;     // admitted this step, source being prepared
+static const int COL_RETIRE = 6;  // leaving this step
+enum { REQ_QUEUED = 0, REQ_RUNNING = 1, REQ_DONE = 2 };
+
+struct Session;
+
+struct Request {
+    uint64_t ticket = 0;
+    bq_gauge g = nullptr;
+    double kappa = 0, csw = 0, mu = 0, tol = 0;
+    int nrhs = 0, prec = 0, maxiter = 0;
+    const double* b = nullptr;  // canonical host sources (owned by the caller until retirement)
+    double* x_host = nullptr;
+    bq_op op = nullptr;
+    Session* sess = nullptr;
+    std::vector<int> slots;
+    int state = REQ_QUEUED;
+    int rc = BQ_OK;
+    std::vector<bq_solve_info> info;
+};
+
+struct Session {
+    bq_gauge g = nullptr;
+    double mu = 0;
+    int prec = 0, cap = 0;
+    hipStream_t st = nullptr;
+    bq_op_s stub;  // gauge and mu for the launch helpers (no clover of its own)
+    Workspace w;
+    DevBuf dbf, sbf, dxf, sxf, stage, dflags;
+    Vec bfull, xfull;
+    ColTable ct{};
+    std::vector<Request*> slot;
+    int* hflags = nullptr;     // pinned: selection flags (cap ints) then per-column tol^2 (cap doubles)
+    double* htol2 = nullptr;
+    int used = 0;
+    ~Session()
+    {
+        if (hflags) (void)hipHostFree(hflags);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+struct bq_server_s {
+    bq_context ctx = nullptr;
+    int cap = 16, chunk = 16;
+    std::vector<std::unique_ptr<Session>> sessions;
+    std::vector<Request*> queue;  // FIFO
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    uint64_t next = 1;
+};
+
+static FieldArg col_arg(const Vec& v, int half, int col)
+{
+    FieldArg a = v.half(half);
+    a.d = (char*)a.d + (size_t)col * v.cstride * unit_bytes(v.prec);
+    if (a.s) a.s += (size_t)col * v.sstride;
+    return a;
+}
+
+static int session_get(bq_server S, bq_gauge g, double mu, int prec, Session** out)
+{
+    for (auto& s : S->sessions)
+        if (s->g == g && s->mu == mu && s->prec == prec) {
+            *out = s.get();
+            return BQ_OK;
+        }
+    auto s = std::make_unique<Session>();
+    s->g = g;
+    s->mu = mu;
+    s->prec = prec;
+    s->cap = S->cap;
+    s->stub.gauge = g;
+    s->stub.mu = mu;
+    bq_context ctx = S->ctx;
+    CHK(ws_init(ctx, g->g, s->cap, prec, 0, &s->w));
+    s->w.ct = &s->ct;
+    CHK(alloc_vec(ctx, g->g, PREC_F64, 2, s->cap, s->dbf, s->sbf, s->bfull));
+    CHK(alloc_vec(ctx, g->g, PREC_F64, 2, s->cap, s->dxf, s->sxf, s->xfull));
+    CHK(s->dflags.alloc(ctx, sizeof(int) * s->cap + sizeof(double) * s->cap));
+    HIPCHK(hipHostMalloc((void**)&s->hflags, sizeof(int) * s->cap + sizeof(double) * s->cap));
+    s->htol2 = (double*)(s->hflags + s->cap);
+    HIPCHK(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    s->slot.assign(s->cap, nullptr);
+    // every slot starts empty: status DONE is inactive for every kernel
+    std::vector<int> st(s->cap, COL_DONE);
+    HIPCHK(hipMemcpy(s->w.cs.status, st.data(), sizeof(int) * s->cap, hipMemcpyHostToDevice));
+    *out = s.get();
+    S->sessions.push_back(std::move(s));
+    return BQ_OK;
+}
+
+// device pointers to the selection flags and per-column tol^2 of a session
+static int* dsel(Session* s) { return s->dflags.as<int>(); }
+static double* dtol2(Session* s) { return (double*)(s->dflags.as<int>() + s->cap); }
+
+static int admit(bq_server S, Request* q, Session* s)
+{
+    bq_context ctx = S->ctx;
+    const Geom& g = s->g->g;
+    CHK(op_build(q->g, q->kappa, q->csw, q->mu, s->prec == PREC_F64 ? PREC_F64 : s->prec, &q->op));
+    const size_t V = 2 * (size_t)g.Vh;
+    const size_t bytes = (size_t)q->nrhs * V * 12 * 16;
+    if (s->stage.bytes < bytes) CHK(s->stage.alloc(ctx, bytes));
+    HIPCHK(hipMemcpyAsync(s->stage.p, q->b, bytes, hipMemcpyHostToDevice, s->st));
+    q->slots.clear();
+    for (int c = 0, k = 0; c < s->cap && k < q->nrhs; c++)
+        if (!s->slot[c]) {
+            s->slot[c] = q;
+            q->slots.push_back(c);
+            const double2* canon = s->stage.as<double2>() + (size_t)k * V * 12;
+            for (int p = 0; p < 2; p++)
+                HIPCHK(launch_spinor_import(canon, 1, g, p, PREC_F64, col_arg(s->bfull, p, c), s->st));
+            for (int pr = 0; pr < 3; pr++) {
+                s->ct.T[pr][1][c] = q->op->T[pr][1].p;
+                s->ct.T[pr][0][c] = q->op->T[pr][0].p;
+                s->ct.Tinv[pr][0][c] = q->op->Tinv[pr][0].p;
+            }
+            s->ct.kappa[c] = q->kappa;
+            s->hflags[c] = 1;
+            s->htol2[c] = q->tol * q->tol;
+            k++;
+        }
+    s->used += q->nrhs;
+    q->sess = s;
+    q->state = REQ_RUNNING;
+    return BQ_OK;
+}
+
+// prepare the columns flagged in hflags: b' = Mhat^dag (b_o + kappa D_oe T_ee^-1 b_e), CG state
+static int prepare_new(Session* s)
+{
+    const int cap = s->cap;
+    Workspace* w = &s->w;
+    hipStream_t st = s->st;
+    HIPCHK(hipMemcpyAsync(s->dflags.p, s->hflags, sizeof(int) * cap + sizeof(double) * cap, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_set_status(w->cs.status, dsel(s), cap, COL_NEW, st));
+    const int m = 1 << COL_NEW;
+    OpCall c64{&s->stub, PREC_F64, get_tune(s->g->ctx, PREC_F64, cap), cap, w->cs.status, m, st};
+    c64.ct = &s->ct;
+    const void* tinv[kMaxCols];
+    for (int c = 0; c < cap; c++) tinv[c] = s->ct.Tinv[PREC_F64][0][c];
+    HIPCHK(launch_clover_apply(PREC_F64, s->g->g, nullptr, s->bfull.half(0), w->t64.all(), cap, st, tinv, w->cs.status, m));
+    CHK(hopv(c64, 0, 1, w->t64.all(), w->q64.all(), s->bfull.half(1), 1.0, 0.0, FK_KAPPA));
+    CHK(k1(c64, 1, w->q64.all(), w->t64.all()));
+    CHK(tv(c64, 1, 1, w->t64.all(), w->q64.all(), w->bp.all(), 0.0, nullptr, 0, 0, FK_MKAPPA2));
+    const int n = w->x.sites();
+    HIPCHK(launch_zero(PREC_F64, w->x.all(), n, cap, w->cs.status, m, st));
+    HIPCHK(launch_convert(PREC_F64, w->bp.all(), PREC_F64, w->r.all(), n, cap, w->cs.status, m, st));
+    if (s->prec != PREC_F64) {
+        HIPCHK(launch_zero(w->xs.prec, w->xs.all(), n, cap, w->cs.status, m, st));
+        HIPCHK(launch_convert(PREC_F64, w->bp.all(), w->rs.prec, w->rs.all(), n, cap, w->cs.status, m, st));
+        HIPCHK(launch_convert(w->rs.prec, w->rs.all(), w->ps.prec, w->ps.all(), n, cap, w->cs.status, m, st));
+    } else {
+        HIPCHK(launch_convert(PREC_F64, w->bp.all(), PREC_F64, w->ps.all(), n, cap, w->cs.status, m, st));
+    }
+    HIPCHK(launch_norm2(PREC_F64, w->bp.all(), n, cap, w->partial, w->pstride, st));
+    HIPCHK(launch_fin_sum(w->partial, w->pstride, cap, w->dtmp, st));
+    HIPCHK(launch_cg_init(w->cs, cap, 0.0, st, dsel(s), dtol2(s), w->dtmp));
+    return BQ_OK;
+}
+
+// retire the requests in `done` (all on session s): fold, residual check, reconstruct, copy out
+static int retire(bq_server S, Session* s, std::vector<Request*>& done)
+{
+    (void)S;
+    const int cap = s->cap;
+    Workspace* w = &s->w;
+    hipStream_t st = s->st;
+    for (int c = 0; c < cap; c++) s->hflags[c] = 0;
+    for (Request* q : done)
+        for (int c : q->slots) s->hflags[c] = 1;
+    HIPCHK(hipMemcpyAsync(s->dflags.p, s->hflags, sizeof(int) * cap, hipMemcpyHostToDevice, st));
+    const int n = w->x.sites();
+    // columns that stopped on maxiter still hold an inner iterate: fold it in (it is 0 for
+    // columns that converged, whose last reliable update folded it)
+    HIPCHK(launch_set_status(w->cs.status, dsel(s), cap, COL_RETIRE, st));
+    const int m = 1 << COL_RETIRE;
+    if (s->prec != PREC_F64) HIPCHK(launch_accum(w->xs.prec, w->xs.all(), w->x.all(), n, cap, w->cs.status, m, st));
+    CHK(true_residual(&s->stub, w, w->cs.status, m, st));
+    HIPCHK(launch_fin_sum(w->partial, w->pstride, cap, w->dtmp, st));
+    HIPCHK(launch_norm2(PREC_F64, w->bp.all(), n, cap, w->partial, w->pstride, st));
+    HIPCHK(launch_fin_sum(w->partial, w->pstride, cap, w->dtmp + cap, st));
+    // x_o into the full solution, x_e = T_ee^-1 (b_e + kappa D_eo x_o)
+    HIPCHK(launch_convert(PREC_F64, w->x.all(), PREC_F64, s->xfull.half(1), n, cap, w->cs.status, m, st));
+    OpCall c64{&s->stub, PREC_F64, get_tune(s->g->ctx, PREC_F64, cap), cap, w->cs.status, m, st};
+    c64.ct = &s->ct;
+    CHK(k1(c64, 0, s->xfull.half(1), s->xfull.half(0), s->bfull.half(0), 1.0, 0.0, FK_KAPPA));
+    std::vector<double> h(2 * cap);
+    std::vector<int> hi(4 * cap);
+    HIPCHK(hipMemcpyAsync(h.data(), w->dtmp, sizeof(double) * 2 * cap, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hi.data(), w->cs.status, sizeof(int) * 4 * cap, hipMemcpyDeviceToHost, st));
+    const Geom& g = s->g->g;
+    const size_t V = 2 * (size_t)g.Vh;
+    for (Request* q : done) {
+        const size_t bytes = (size_t)q->nrhs * V * 12 * 16;
+        if (s->stage.bytes < bytes) CHK(s->stage.alloc(S->ctx, bytes));
+        for (size_t k = 0; k < q->slots.size(); k++)
+            for (int p = 0; p < 2; p++)
+                HIPCHK(launch_spinor_export(col_arg(s->xfull, p, q->slots[k]), 1, g, p, PREC_F64,
+                                            s->stage.as<double2>() + k * V * 12, st));
+        HIPCHK(hipMemcpyAsync(q->x_host, s->stage.p, bytes, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (Request* q : done) {
+        q->info.assign(q->nrhs, bq_solve_info{});
+        q->rc = BQ_OK;
+        for (size_t k = 0; k < q->slots.size(); k++) {
+            const int c = q->slots[k];
+            const double tr = h[cap + c] > 0 ? std::sqrt(h[c] / h[cap + c]) : 0.0;
+            bq_solve_info& in = q->info[k];
+            in.iters = hi[cap + c];
+            in.reliable_updates = hi[3 * cap + c];
+            in.true_rel_resid = tr;
+            in.full_rel_resid = tr;
+            in.converged = std::isfinite(tr) && tr <= q->tol;
+            in.status = !std::isfinite(tr) ? BQ_ERR_NONFINITE : (in.converged ? BQ_OK : BQ_ERR_NOT_CONVERGED);
+            if (in.status != BQ_OK && q->rc == BQ_OK) q->rc = in.status;
+            s->slot[c] = nullptr;
+            for (int pr = 0; pr < 3; pr++) s->ct.T[pr][0][c] = s->ct.T[pr][1][c] = s->ct.Tinv[pr][0][c] = nullptr;
+        }
+        s->used -= q->nrhs;
+        bq_op_free(q->op);
+        q->op = nullptr;
+        q->state = REQ_DONE;
+    }
+    HIPCHK(launch_set_status(w->cs.status, dsel(s), cap, COL_DONE, st));
+    return BQ_OK;
+}
+
+extern "C" {
+
+int bq_server_create(bq_context ctx, int slots, int chunk, bq_server* out)
+{
+    if (!ctx || !out) return fail(BQ_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (slots < 1 || slots > kMaxCols) return fail(BQ_ERR_INVALID, "slots must be in 1..%d", kMaxCols);
+    auto S = std::make_unique<bq_server_s>();
+    S->ctx = ctx;
+    S->cap = slots;
+    S->chunk = chunk > 0 ? chunk : 16;
+    *out = S.release();
+    return BQ_OK;
+}
+
+int bq_server_submit(bq_server S, bq_gauge g, double kappa, double csw, double mu, const double* b, double* x,
+                     int nrhs, double tol, int inner_prec, int maxiter, uint64_t* ticket)
+{
+    if (!S || !g || !b || !x || !ticket) return fail(BQ_ERR_INVALID, "NULL argument");
+    if (g->ctx != S->ctx) return fail(BQ_ERR_INVALID, "gauge field of another context");
+    if (nrhs < 1 || nrhs > S->cap) return fail(BQ_ERR_INVALID, "nrhs must be in 1..%d", S->cap);
+    if (!(tol > 0)) return fail(BQ_ERR_INVALID, "tol must be > 0");
+    if (inner_prec < BQ_F64 || inner_prec > BQ_F16) return fail(BQ_ERR_INVALID, "bad inner precision");
+    auto q = std::make_unique<Request>();
+    q->ticket = S->next++;
+    q->g = g;
+    q->kappa = kappa;
+    q->csw = csw;
+    q->mu = mu;
+    q->tol = tol;
+    q->nrhs = nrhs;
+    q->prec = inner_prec;
+    q->maxiter = maxiter > 0 ? maxiter : 100000;
+    q->b = b;
+    q->x_host = x;
+    *ticket = q->ticket;
+    S->queue.push_back(q.get());
+    S->reqs[q->ticket] = std::move(q);
+    return BQ_OK;
+}
+
+int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone)
+{
+    if (!S || !ndone) return fail(BQ_ERR_INVALID, "NULL argument");
+    *ndone = 0;
+    bq_context ctx = S->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    // 1. admission, FIFO per session (a request that does not fit waits; others may pass it)
+    std::vector<Session*> fresh;
+    std::vector<Request*> keep;
+    std::map<Session*, bool> blocked;
+    for (Request* q : S->queue) {
+        Session* s = nullptr;
+        int rc = session_get(S, q->g, q->mu, q->prec, &s);
+        if (rc == BQ_ERR_OOM) {
+            keep.push_back(q);
+            continue;
+        }
+        if (rc != BQ_OK) return rc;
+        if (blocked[s] || s->cap - s->used < q->nrhs) {
+            blocked[s] = true;
+            keep.push_back(q);
+            continue;
+        }
+        if (std::find(fresh.begin(), fresh.end(), s) == fresh.end()) {
+            for (int c = 0; c < s->cap; c++) s->hflags[c] = 0;
+            fresh.push_back(s);
+        }
+        rc = admit(S, q, s);
+        if (rc == BQ_ERR_OOM) {  // no room for the operator now: undo and wait
+            for (int c : q->slots) {
+                s->slot[c] = nullptr;
+                s->hflags[c] = 0;
+            }
+            if (q->op) bq_op_free(q->op);
+            q->op = nullptr;
+            q->slots.clear();
+            q->state = REQ_QUEUED;
+            blocked[s] = true;
+            keep.push_back(q);
+            continue;
+        }
+        if (rc != BQ_OK) return rc;
+    }
+    S->queue = keep;
+    for (Session* s : fresh) CHK(prepare_new(s));
+    // 2. one chunk on every session with work, all launched before any wait
+    std::vector<Session*> run;
+    for (auto& s : S->sessions)
+        if (s->used > 0) {
+            Workspace* w = &s->w;
+            w->cs.delta2 = s->prec == PREC_F64 ? 0.0 : 0.01;
+            CHK(chunk(&s->stub, w, s->prec, S->chunk, s->st));
+            HIPCHK(hipMemcpyAsync(w->h_status, w->cs.status, sizeof(int) * 4 * s->cap, hipMemcpyDeviceToHost, s->st));
+            run.push_back(s.get());
+        }
+    // 3. retire finished requests
+    for (Session* s : run) {
+        HIPCHK(hipStreamSynchronize(s->st));
+        const int* hs = s->w.h_status;
+        std::vector<Request*> done;
+        for (int c = 0; c < s->cap; c++) {
+            Request* q = s->slot[c];
+            if (!q || std::find(done.begin(), done.end(), q) != done.end()) continue;
+            bool fin = true;
+            for (int cc : q->slots) {
+                const int stc = hs[cc];
+                const bool out_of_iters = hs[s->cap + cc] >= q->maxiter;
+                if (!(stc == COL_DONE || stc == COL_FAILED || out_of_iters)) fin = false;
+            }
+            if (fin) done.push_back(q);
+        }
+        if (!done.empty()) {
+            CHK(retire(S, s, done));
+            for (Request* q : done)
+                if (*ndone < max_done && done_tickets) done_tickets[(*ndone)++] = q->ticket;
+                else (*ndone)++;
+        }
+    }
+    return BQ_OK;
+}
+
+int bq_server_result(bq_server S, uint64_t ticket, bq_solve_info* info)
+{
+    if (!S) return fail(BQ_ERR_INVALID, "NULL argument");
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(BQ_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* q = it->second.get();
+    if (q->state != REQ_DONE) return BQ_PENDING;
+    if (info)
+        for (int k = 0; k < q->nrhs; k++) info[k] = q->info[k];
+    const int rc = q->rc;
+    S->reqs.erase(it);
+    return rc;
+}
+
+int bq_server_pending(bq_server S, int* queued, int* running)
+{
+    if (!S || !queued || !running) return fail(BQ_ERR_INVALID, "NULL argument");
+    *queued = (int)S->queue.size();
+    int r = 0;
+    for (auto& kv : S->reqs)
+        if (kv.second->state == REQ_RUNNING) r++;
+    *running = r;
+    return BQ_OK;
+}
+
+int bq_server_free(bq_server S)
+{
+    if (!S) return BQ_OK;
+    (void)hipSetDevice(S->ctx->device);
+    for (auto& kv : S->reqs)
+        if (kv.second->op) bq_op_free(kv.second->op);
+    for (auto& s : S->sessions) (void)hipStreamSynchronize(s->st);
+    delete S;
     return BQ_OK;
 }
 

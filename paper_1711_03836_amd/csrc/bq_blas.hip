@@ -539,12 +539,14 @@ hipError_t launch_fin_sum(const double* partial, int nwaves, int ncol, double* o
 
 namespace bq {
 namespace {
-__global__ void k_cg_init(const CgScalars s, int ncol, double tol2)
+__global__ void k_cg_init(const CgScalars s, int ncol, double tol2, const int* sel, const double* tol2c,
+                          const double* rho_src)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncol) return;
+    if (c >= ncol || (sel && !sel[c])) return;
+    if (rho_src) s.rho[c] = rho_src[c];
     const double r2 = s.rho[c];
-    s.stop2[c] = tol2 * r2;
+    s.stop2[c] = (tol2c ? tol2c[c] : tol2) * r2;
     s.rmax2[c] = r2;
     s.iters[c] = 0;
     s.nrel[c] = 0;
@@ -555,9 +557,22 @@ __global__ void k_cg_init(const CgScalars s, int ncol, double tol2)
 }
 }  // namespace
 
-hipError_t launch_cg_init(const CgScalars& s, int ncol, double tol2, hipStream_t st)
+hipError_t launch_cg_init(const CgScalars& s, int ncol, double tol2, hipStream_t st, const int* sel,
+                          const double* tol2c, const double* rho_src)
 {
-    hipLaunchKernelGGL(k_cg_init, dim3((ncol + 63) / 64), dim3(64), 0, st, s, ncol, tol2);
+    hipLaunchKernelGGL(k_cg_init, dim3((ncol + 63) / 64), dim3(64), 0, st, s, ncol, tol2, sel, tol2c, rho_src);
+    return hipGetLastError();
+}
+
+__global__ void k_set_status(int* status, const int* sel, int ncol, int value)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncol && sel[c]) status[c] = value;
+}
+
+hipError_t launch_set_status(int* status, const int* sel, int ncol, int value, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_status, dim3((ncol + 63) / 64), dim3(64), 0, st, status, sel, ncol, value);
     return hipGetLastError();
 }
 }  // namespace bq

@@ -339,13 +339,19 @@ __global__ __launch_bounds__(64) void k_clover_from_B(const Geom g, const double
     if (!ok && bad) *bad = 1;
 }
 
+struct CloverCols {
+    const void* p[kMaxCols];
+};
+
 template <class P>
-__global__ void k_clover_apply(const Geom g, const typename P::unit* C, SpinorPtr<P> in, SpinorPtr<P> out, int ncol)
+__global__ void k_clover_apply(const Geom g, const typename P::unit* C0, SpinorPtr<P> in, SpinorPtr<P> out, int ncol,
+                               int percol, const CloverCols cc, const int* status, int statmask)
 {
     using T = typename P::real;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
-    if (j >= g.Vh || c >= ncol) return;
+    if (j >= g.Vh || c >= ncol || (status && !col_selected(status, statmask, c))) return;
+    const typename P::unit* C = percol ? (const typename P::unit*)cc.p[c] : C0;
     cx<T> v[12], y[12];
     load_spinor(in, c, j, v);
 #pragma unroll
@@ -458,25 +464,31 @@ hipError_t launch_clover_from_B(const Geom& g, int parity, const double2* B, dou
 }
 
 hipError_t launch_clover_apply(int prec, const Geom& g, const void* clov, FieldArg in, FieldArg out, int ncol,
-                               hipStream_t st)
+                               hipStream_t st, const void* const* cclov, const int* status, int statmask)
 {
     const int bs = 128;
     dim3 grid((g.Vh + bs - 1) / bs, ncol);
+    CloverCols cc{};
+    const int percol = cclov != nullptr;
+    if (percol) {
+        if (ncol > kMaxCols) return hipErrorInvalidValue;
+        for (int c = 0; c < ncol; c++) cc.p[c] = cclov[c];
+    }
     switch (prec) {
     case PREC_F64:
         hipLaunchKernelGGL(k_clover_apply<P64>, grid, dim3(bs), 0, st, g, (const double2*)clov,
                            SpinorPtr<P64>{(double2*)in.d, in.s, in.cstride, in.sstride},
-                           SpinorPtr<P64>{(double2*)out.d, out.s, out.cstride, out.sstride}, ncol);
+                           SpinorPtr<P64>{(double2*)out.d, out.s, out.cstride, out.sstride}, ncol, percol, cc, status, statmask);
         break;
     case PREC_F32:
         hipLaunchKernelGGL(k_clover_apply<P32>, grid, dim3(bs), 0, st, g, (const float2*)clov,
                            SpinorPtr<P32>{(float2*)in.d, in.s, in.cstride, in.sstride},
-                           SpinorPtr<P32>{(float2*)out.d, out.s, out.cstride, out.sstride}, ncol);
+                           SpinorPtr<P32>{(float2*)out.d, out.s, out.cstride, out.sstride}, ncol, percol, cc, status, statmask);
         break;
     case PREC_F16:
         hipLaunchKernelGGL(k_clover_apply<P16>, grid, dim3(bs), 0, st, g, (const uint2*)clov,
                            SpinorPtr<P16>{(uint2*)in.d, in.s, in.cstride, in.sstride},
-                           SpinorPtr<P16>{(uint2*)out.d, out.s, out.cstride, out.sstride}, ncol);
+                           SpinorPtr<P16>{(uint2*)out.d, out.s, out.cstride, out.sstride}, ncol, percol, cc, status, statmask);
         break;
     default: return hipErrorInvalidValue;
     }

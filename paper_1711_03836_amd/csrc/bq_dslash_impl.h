@@ -209,7 +209,18 @@ struct Args {
     int statmask;
     typename P::real ef, eb, ef_bc, eb_bc;  // time coefficients, without / with the boundary sign
     typename P::real f, a;
+    // per-column operators (columns of different kappa on one gauge field): clover blocks and f
+    int percol;
+    const typename P::unit* cclov[kMaxCols];
+    typename P::real cf[kMaxCols];
 };
+
+template <bool PC, class P, class PR>
+__device__ __forceinline__ typename P::real colf(const Args<P, PR>& A, int c)
+{
+    if constexpr (PC) return A.cf[c];
+    else return A.f;
+}
 
 // End of one hop's phase.  Without it the compiler issues the loads of all
 // eight hops first and sinks their arithmetic to the end of the kernel, which
@@ -279,7 +290,7 @@ __device__ __forceinline__ void hop_dir(const Args<P, PR>& A, const Site& s, con
 // One work item: tile block `tblk` (tpb tiles) x column-group chunk `chunk` (gw groups of R
 // columns).  Wave w of the workgroup handles tile w / gw and group w % gw, so all groups of a
 // tile run side by side and share the links and clover through L1/L2.
-template <class P, class PR, int R, int DAG, int EPI, int RECON>
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
 __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chunk)
 {
     using T = typename P::real;
@@ -321,24 +332,26 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (!act[r]) continue;
+                const T f = colf<PC>(A, c0 + r);
                 if (A.v.d != nullptr) {
                     cx<T> v[12];
                     load_spinor(A.v, c0 + r, j, v);
 #pragma unroll
-                    for (int k = 0; k < 12; k++) acc[r][k] = caxpy(A.f, acc[r][k], cscale(A.a, v[k]));
+                    for (int k = 0; k < 12; k++) acc[r][k] = caxpy(f, acc[r][k], cscale(A.a, v[k]));
                 } else {
 #pragma unroll
-                    for (int k = 0; k < 12; k++) acc[r][k] = cscale(A.f, acc[r][k]);
+                    for (int k = 0; k < 12; k++) acc[r][k] = cscale(f, acc[r][k]);
                 }
             }
             if constexpr (EPI == EPI_TINV) {
 #pragma unroll
                 for (int blk = 0; blk < 2; blk++) {
                     cx<T> cb[18];
-                    load_clover_block<P>(A.clov, j, blk, cb);
+                    if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
 #pragma unroll
                     for (int r = 0; r < R; r++) {
                         if (!act[r]) continue;
+                        if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
                         cx<T> x[6];
 #pragma unroll
                         for (int k = 0; k < 6; k++) x[k] = acc[r][blk * 6 + k];
@@ -355,15 +368,17 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
 #pragma unroll
             for (int blk = 0; blk < 2; blk++) {
                 cx<T> cb[18];
-                load_clover_block<P>(A.clov, j, blk, cb);
+                if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     if (!act[r]) continue;
+                    if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
+                    const T f = colf<PC>(A, c0 + r);
                     cx<T> x[6], y[6];
                     load_spinor_part(A.v, c0 + r, j, blk, x);
                     clover_mul(cb, x, y);
 #pragma unroll
-                    for (int k = 0; k < 6; k++) acc[r][blk * 6 + k] = caxpy(A.f, acc[r][blk * 6 + k], y[k]);
+                    for (int k = 0; k < 6; k++) acc[r][blk * 6 + k] = caxpy(f, acc[r][blk * 6 + k], y[k]);
                 }
                 phase_end(act, acc);
             }
@@ -382,11 +397,13 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
 #pragma unroll
             for (int blk = 0; blk < 2; blk++) {
                 cx<T> cb[18];
-                load_clover_block<P>(A.clov, j, blk, cb);
+                if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     if (!act[r]) continue;
                     const int c = c0 + r;
+                    if constexpr (PC) load_clover_block<P>(A.cclov[c], j, blk, cb);
+                    const T f = colf<PC>(A, c);
                     const TR al = A.alpha ? (TR)A.alpha[c] : TR(1);
                     cx<T> x[6], y[6];
                     load_spinor_part(A.v, c, j, blk, x);
@@ -397,7 +414,7 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
                     double n = 0.0;
 #pragma unroll
                     for (int k = 0; k < 6; k++) {
-                        const cx<T> w = caxpy(A.f, acc[r][blk * 6 + k], y[k]);
+                        const cx<T> w = caxpy(f, acc[r][blk * 6 + k], y[k]);
                         rv[k].re = fmadd(-al, (TR)w.re, rv[k].re);
                         rv[k].im = fmadd(-al, (TR)w.im, rv[k].im);
                         st_stream(&rb[toff(j, blk * 6 + k, 12)], {rv[k].re, rv[k].im});
@@ -426,12 +443,12 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
 
 
 // One work item per workgroup; blocks are mapped XCD-contiguously (see xcd_remap).
-template <class P, class PR, int R, int DAG, int EPI, int RECON>
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
 __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
 {
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int tblk = lb / A.nch;
-    hop_item<P, PR, R, DAG, EPI, RECON>(A, tblk, lb - tblk * A.nch);
+    hop_item<P, PR, R, DAG, EPI, RECON, PC>(A, tblk, lb - tblk * A.nch);
 }
 
 template <class P>
@@ -440,7 +457,7 @@ SpinorPtr<P> sp(const FieldArg& f)
     return SpinorPtr<P>{(typename P::unit*)f.d, f.s, f.cstride, f.sstride};
 }
 
-template <class P, class PR, int R, int DAG, int EPI, int RECON>
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
 hipError_t launch_t(const HopLaunch& L, hipStream_t st)
 {
     using T = typename P::real;
@@ -467,6 +484,12 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
     A.eb_bc = (T)(L.eb * L.tbc);
     A.f = (T)L.f;
     A.a = (T)L.a;
+    A.percol = L.percol;
+    for (int c = 0; c < kMaxCols; c++) {
+        A.cclov[c] = (const typename P::unit*)L.cclov[c];
+        A.cf[c] = (T)L.cf[c];
+    }
+    if (L.percol && L.ncol > kMaxCols) return hipErrorInvalidValue;
     // L.bs = sites per workgroup (a multiple of 64); at most 512 threads per workgroup
     const int G = (L.ncol + R - 1) / R;
     const int tpb = std::max(1, L.bs / kTile);
@@ -474,19 +497,24 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
     A.gw = std::max(1, std::min(G, 512 / (tpb * kTile)));
     A.nch = (G + A.gw - 1) / A.gw;
     A.nblk = (L.g.ntiles + tpb - 1) / tpb;
-    hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON>), dim3(A.nblk * A.nch), dim3(tpb * kTile * A.gw), 0, st, A);
+    hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON, PC>), dim3(A.nblk * A.nch), dim3(tpb * kTile * A.gw), 0, st, A);
     return hipGetLastError();
 }
 
+// per-column operators (kappa-batched serving) are instantiated for 12-real links only
 template <class P, class PR, int R, int DAG, int EPI>
 hipError_t by_recon(const HopLaunch& L, hipStream_t st)
 {
+    if (L.percol) {
+        if (L.recon != 12) return hipErrorInvalidValue;
+        return launch_t<P, PR, R, DAG, EPI, 12, true>(L, st);
+    }
     if constexpr (P::id == PREC_F16) {
         if (L.recon != 12) return hipErrorInvalidValue;
-        return launch_t<P, PR, R, DAG, EPI, 12>(L, st);
+        return launch_t<P, PR, R, DAG, EPI, 12, false>(L, st);
     } else {
-        if (L.recon == 12) return launch_t<P, PR, R, DAG, EPI, 12>(L, st);
-        if (L.recon == 18) return launch_t<P, PR, R, DAG, EPI, 18>(L, st);
+        if (L.recon == 12) return launch_t<P, PR, R, DAG, EPI, 12, false>(L, st);
+        if (L.recon == 18) return launch_t<P, PR, R, DAG, EPI, 18, false>(L, st);
         return hipErrorInvalidValue;
     }
 }

@@ -18,6 +18,9 @@ enum {
     EPI_TVR = 3,   // w = C v + f*hop; r_out = r_in - alpha*w (+ |r_out|^2 partials)  (CG residual update)
 };
 
+// most columns one launch can give their own operator (kappa, clover)
+constexpr int kMaxCols = 32;
+
 struct FieldArg {
     void* d = nullptr;       // storage units
     float* s = nullptr;      // FP16 per-site scales
@@ -48,6 +51,9 @@ struct HopLaunch {
     double ef = 1, eb = 1;   // time-hop coefficients of the forward / backward term
     int tbc = -1;
     double f = 1, a = 0;
+    int percol = 0;                    // 1: column c uses cclov[c] and cf[c] instead of clov and f
+    const void* cclov[kMaxCols] = {};
+    double cf[kMaxCols] = {};
 };
 
 hipError_t launch_hop(const HopLaunch& L, hipStream_t st);
@@ -68,7 +74,8 @@ hipError_t launch_clover_build(const CloverBuild& c, hipStream_t st);
 hipError_t launch_clover_from_B(const Geom& g, int parity, const double2* B, double ck, double2* T, double2* Tinv,
                                 int* bad, hipStream_t st);
 hipError_t launch_clover_apply(int prec, const Geom& g, const void* clov, FieldArg in, FieldArg out, int ncol,
-                               hipStream_t st);
+                               hipStream_t st, const void* const* cclov = nullptr, const int* status = nullptr,
+                               int statmask = 0);
 hipError_t launch_clover_convert(int prec, const double2* src, void* dst, int Vh, hipStream_t st);
 
 // layout conversion
@@ -117,7 +124,11 @@ hipError_t launch_fin_alpha(const CgScalars& s, const double* partial, int nwave
 hipError_t launch_fin_beta(const CgScalars& s, const double* partial, int nwaves, int ncol, hipStream_t st);
 hipError_t launch_fin_reliable(const CgScalars& s, const double* partial, int nwaves, int ncol, hipStream_t st);
 hipError_t launch_fin_sum(const double* partial, int nwaves, int ncol, double* out, hipStream_t st);
-// stop2 = tol2 * rho, rmax2 = rho, counters cleared, status from rho (rho holds |b|^2 on entry)
-hipError_t launch_cg_init(const CgScalars& s, int ncol, double tol2, hipStream_t st);
+// stop2 = tol2 * rho, rmax2 = rho, counters cleared, status from rho (rho holds |b|^2 on entry);
+// with `sel` only columns with sel[c] != 0 are initialised, and tol2 is per column (tol2c) if given
+hipError_t launch_cg_init(const CgScalars& s, int ncol, double tol2, hipStream_t st, const int* sel = nullptr,
+                          const double* tol2c = nullptr, const double* rho_src = nullptr);
+// status[c] = value for every column with sel[c] != 0
+hipError_t launch_set_status(int* status, const int* sel, int ncol, int value, hipStream_t st);
 
 }  // namespace bq

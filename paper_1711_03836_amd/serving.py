@@ -1,0 +1,157 @@
+"""Serving workload: many solve requests of mixed lattice sizes and kappa, Poisson arrivals.
+
+  python -m paper_1711_03836_amd.serving --requests 2000 --load 0.8
+
+Gauge fields U = exp(0.2 i H) on 8^4, 16^3x32, 24^3x48 and 32^3x64 stay resident on
+the device.  Each request draws its lattice uniformly from those four, kappa uniform
+in [0.118, 0.124] (c_SW = 1.5, mu = 0), 1-12 right-hand sides and a relative residual
+of 1e-10, and is served by the continuous-batching server of the C library.
+
+Sources: a pool of seeded complex Gaussian fields per lattice is generated once; the
+sources of a request are pool fields shifted cyclically along x by request-dependent
+offsets, so every request has its own Gaussian sources without generating gigabytes
+of random numbers per request.
+
+Latency = completion - arrival (queueing included), on the host clock.  --load L runs
+Poisson arrivals at L x the saturated throughput measured first with every request
+submitted at time zero (--saturation-requests of them); --qps sets the rate directly.
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SIZES = [(8, 8, 8, 8), (16, 16, 16, 32), (24, 24, 24, 48), (32, 32, 32, 64)]
+POOL = 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class World:
+    """Resident gauge fields and source pools for the serving lattices."""
+
+    def __init__(self, bq, ctx, sizes=SIZES, eps=0.2, seed=4, pool=POOL):
+        from paper_1711_03836_amd import inputs
+        self.bq, self.ctx, self.sizes = bq, ctx, [tuple(s) for s in sizes]
+        self.gauges, self.pools = {}, {}
+        for k, d in enumerate(self.sizes):
+            U = inputs.gauge_field(d, eps, seed=seed + k)
+            self.gauges[d] = bq.Gauge(ctx, d, U, t_bc=-1)
+            del U
+            self.pools[d] = inputs.gaussian_spinor(d, pool, seed=100 + k)
+
+    def sources(self, dims, nrhs, rseed):
+        """nrhs sources for one request: pool fields rolled along x by request-dependent amounts."""
+        pool = self.pools[dims]
+        V = int(np.prod(dims))
+        b = np.empty((nrhs, V, 4, 3), dtype=np.complex128)
+        shp = (dims[3], dims[2], dims[1], dims[0], 4, 3)
+        for k in range(nrhs):
+            src = pool[(rseed + k) % len(pool)].reshape(shp)
+            b[k] = np.roll(src, 2 * ((rseed * 7 + k) % (dims[0] // 2)), axis=3).reshape(V, 4, 3)
+        return b
+
+
+def make_requests(n, seed, sizes=SIZES, kappa=(0.118, 0.124), nrhs=(1, 12)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        out.append({"id": i, "dims": tuple(sizes[rng.integers(len(sizes))]),
+                    "kappa": float(rng.uniform(*kappa)), "nrhs": int(rng.integers(nrhs[0], nrhs[1] + 1)),
+                    "rseed": int(rng.integers(1 << 30))})
+    return out
+
+
+def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_prec=1, progress=50):
+    """Serve `reqs`; arrivals at time 0 (qps None) or Poisson with rate qps.  Returns a summary dict."""
+    rng = np.random.default_rng(seed)
+    if qps:
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
+        arrivals -= arrivals[0]
+    else:
+        arrivals = np.zeros(len(reqs))
+    t0 = time.perf_counter()
+    nxt, pending, lat, info_worst, ncols = 0, {}, [], 0.0, 0
+    done_count = 0
+    while done_count < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            b = world.sources(r["dims"], r["nrhs"], r["rseed"])
+            tk = server.submit(world.gauges[r["dims"]], b, r["kappa"], csw, 0.0, tol, inner_prec)
+            pending[tk] = (nxt, t0 + arrivals[nxt])
+            nxt += 1
+        if not pending:
+            time.sleep(max(0.0, min(0.01, arrivals[nxt] - now)))
+            continue
+        done = server.step()
+        tdone = time.perf_counter()
+        for tk in done:
+            i, tarr = pending.pop(tk)
+            rc, info, x = server.result(tk)
+            if rc != bq.BQ_OK:
+                raise RuntimeError(f"request {i} failed: {rc} {info}")
+            lat.append(tdone - tarr)
+            info_worst = max(info_worst, max(c["true_rel_resid"] for c in info))
+            ncols += len(info)
+            done_count += 1
+            if progress and done_count % progress == 0:
+                log(f"[serve] {done_count}/{len(reqs)} done, p50 so far {np.percentile(lat, 50):.3f}s")
+    span = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"requests": len(reqs), "rhs": ncols, "seconds": span, "solves_per_s": len(reqs) / span,
+            "rhs_per_s": ncols / span, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "qps": qps, "worst_true_rel_resid": info_worst}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--saturation-requests", type=int, default=200)
+    ap.add_argument("--load", type=float, nargs="*", default=[0.5, 0.8])
+    ap.add_argument("--qps", type=float, default=None)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--inner", choices=["f64", "f32", "f16"], default="f32")
+    ap.add_argument("--seed", type=int, default=2017)
+    args = ap.parse_args()
+
+    from paper_1711_03836_amd import bqhip as bq
+    prec = {"f64": 0, "f32": 1, "f16": 2}[args.inner]
+    ctx = bq.Context(0)
+    log("[serve] building gauge fields and source pools ...")
+    world = World(bq, ctx)
+    out = {"workload": "serving mix: lattices {8^4, 16^3x32, 24^3x48, 32^3x64}, kappa U[0.118,0.124], c_SW 1.5, "
+                       "1-12 Gaussian RHS, tol 1e-10, U=exp(0.2 i H)", "slots": args.slots, "chunk": args.chunk,
+           "inner_prec": args.inner, "runs": []}
+    sat = None
+    if args.qps is None:
+        server = bq.Server(ctx, args.slots, args.chunk)
+        r = run(bq, world, server, make_requests(args.saturation_requests, args.seed + 1), None, inner_prec=prec)
+        server.close()
+        sat = r["solves_per_s"]
+        out["saturation"] = r
+        log(f"[serve] saturated throughput {sat:.2f} requests/s")
+    rates = [args.qps] if args.qps else [f * sat for f in args.load]
+    for q in rates:
+        server = bq.Server(ctx, args.slots, args.chunk)
+        r = run(bq, world, server, make_requests(args.requests, args.seed), q, seed=args.seed, inner_prec=prec)
+        server.close()
+        r["load"] = q / sat if sat else None
+        out["runs"].append(r)
+        log(f"[serve] qps {q:.2f}: p50 {r['p50_s']:.3f}s p99 {r['p99_s']:.3f}s, {r['solves_per_s']:.2f} solves/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
