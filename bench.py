@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=40, help="requests of the short serving run (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -144,10 +146,15 @@ def main():
                         "mdagm_ms": ms2, "mdagm_gbs": by2 / ms2 / 1e6, "tune": ctx.tune_get(prec, nrhs)}
         log(f"[bench] K1 {name} x{nrhs}: {ms:.3f} ms, {by/ms/1e6:.0f} GB/s; Mhat^dag Mhat {by2/ms2/1e6:.0f} GB/s")
     k = dslash[args.inner]
+    traffic, traffic_note = measured_traffic(dims, args.inner, nrhs, k["tune"])
     roof = {"bound": "hbm", "achieved": k["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": k["k1_gbs"] / HBM_PEAK_GBS, "traffic": None,
+            "frac": k["k1_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": f"K1 = T_ee^-1 D_eo, {args.inner}, {nrhs} columns, recon/R/bs={k['tune']}",
-            "bytes_per_launch": k["k1_bytes"]}
+            "bytes_per_launch": k["k1_bytes"], "traffic_source": traffic_note}
+
+    serving = None
+    if args.serve_requests > 0:
+        serving = serve(bq, ctx, args.serve_requests, args.serve_load)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -161,7 +168,7 @@ def main():
                                f"mu={mu}, kappa={kappa}, c_SW={csw}, U=exp({eps} i H), tol {tol:g}, "
                                f"{args.inner} inner + f64 reliable updates",
                    "lattice": list(dims), "nrhs": nrhs, "plaquette": plaq},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "dslash": dslash,
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "dslash": dslash, "serving": serving,
         "solve": {"true_rel_resid": worst_true, "full_rel_resid": worst_full,
                   "iters": max(c["iters"] for c in last_info),
                   "reliable_updates": max(c["reliable_updates"] for c in last_info),
@@ -169,6 +176,45 @@ def main():
                   "bytes_per_solve": last_st["bytes"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(dims, inner, nrhs, tune):
+    """HBM bytes per launch of the timed K1 from the committed FETCH_SIZE / WRITE_SIZE summary, if it was
+    taken on the current kernel sources and the same launch configuration; else None."""
+    from paper_1711_03836_amd.profile_summary import source_digest
+    name = f"k1_{inner}x{nrhs}_{'x'.join(map(str, dims))}_traffic.json"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None, f"no counter summary profiles/{name}"
+    rec = json.load(open(path))
+    if rec.get("source_digest") != source_digest():
+        return None, f"profiles/{name} was taken on other kernel sources"
+    if rec.get("tune") and list(rec["tune"]) != list(tune):
+        return None, f"profiles/{name} was taken with recon/R/bs={rec['tune']}, this run uses {list(tune)}"
+    return rec["traffic_bytes"], f"profiles/{name} (FETCH_SIZE x{rec['fetch']['factor']:.3f} + WRITE_SIZE " \
+                                 f"x{rec['write']['factor']:.3f}, copy-calibrated)"
+
+
+def serve(bq, ctx, nreq, load):
+    """Short continuous-batching run of the serving mix: saturated throughput from nreq/2 requests
+    submitted at once, then nreq Poisson arrivals at `load` x that rate; p50/p99 latency."""
+    from paper_1711_03836_amd import serving
+    log(f"[bench] serving: building resident gauge fields for {serving.SIZES}")
+    world = serving.World(bq, ctx)
+    server = bq.Server(ctx, 16, 16)
+    sat = serving.run(bq, world, server, serving.make_requests(max(8, nreq // 2), 2018), None, progress=0)
+    server.close()
+    qps = load * sat["solves_per_s"]
+    server = bq.Server(ctx, 16, 16)
+    r = serving.run(bq, world, server, serving.make_requests(nreq, 2017), qps, seed=2017, progress=0)
+    server.close()
+    log(f"[bench] serving: saturated {sat['solves_per_s']:.2f} req/s; at {load} load p50 {r['p50_s']:.3f}s "
+        f"p99 {r['p99_s']:.3f}s")
+    return {"saturated_solves_per_s": sat["solves_per_s"], "saturated_rhs_per_s": sat["rhs_per_s"],
+            "load": load, "qps": qps, "requests": nreq, "p50_s": r["p50_s"], "p99_s": r["p99_s"],
+            "solves_per_s": r["solves_per_s"], "worst_true_rel_resid": max(r["worst_true_rel_resid"],
+                                                                             sat["worst_true_rel_resid"]),
+            "mix": "lattices {8^4, 16^3x32, 24^3x48, 32^3x64}, kappa U[0.118,0.124], c_SW 1.5, 1-12 RHS, tol 1e-10"}
 
 
 def cpu_baseline(dims, U, kappa, csw, mu, b, op, inner):

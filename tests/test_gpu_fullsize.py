@@ -1,0 +1,94 @@
+"""The 32^3x64 multi-column workload at full size, in the launch configuration the autotuner picks.
+
+The oracle cannot apply the operator to whole 32^3x64 fields in test time, so it computes sampled
+outputs one by one from their definition (Mhat and Mhat^dag at odd sites, M at any site).  Checked:
+  - Mhat and Mhat^dag on 12 FP32 Gaussian columns at sampled sites, 1e-5 relative to the largest
+    sampled reference element (the FP32 field-agreement bar);
+  - the 12 point-source solve (FP32 inner, FP64 reliable updates, tol 1e-10): at every sampled site
+    the residual b - M x, computed by the oracle from the GPU solution, is bounded by the global
+    residual norm the library reports, and that norm is small.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1711_03836_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (32, 32, 32, 64)
+KAPPA, CSW, MU, EPS = 0.124, 1.5, 0.1, 0.2
+
+
+def _sample_sites(rng, parity, n):
+    """n sites of the given parity (None: any), including the time and space boundaries."""
+    L = DIMS
+    pts = [(0, 0, 0, 0), (L[0] - 1, 0, 0, 0), (0, L[1] - 1, 0, L[3] - 1), (1, 2, 3, L[3] - 1),
+           (L[0] - 1, L[1] - 1, L[2] - 1, L[3] - 1), (5, 0, L[2] - 1, 0)]
+    while len(pts) < 4 * n:
+        pts.append(tuple(int(rng.integers(l)) for l in L))
+    out = []
+    for x in pts:
+        lex = x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3]))
+        if parity is None or sum(x) % 2 == parity:
+            out.append(lex)
+        if len(out) == n:
+            break
+    return np.array(sorted(set(out)), dtype=np.int64)
+
+
+@pytest.fixture(scope="module")
+def world():
+    from paper_1711_03836_amd import bqhip as bq
+    U = inputs.gauge_field(DIMS, EPS, seed=20171110)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, DIMS, U, -1)
+    op = bq.Op(G, KAPPA, CSW, MU)
+    op.autotune(bq.BQ_F32, 12)
+    print(f"[fullsize] tune f32 x12 = {ctx.tune_get(bq.BQ_F32, 12)}", flush=True)
+    return bq, U, ctx, G, op
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dagger", [False, True])
+def test_mhat_sampled(world, dagger):
+    bq, U, ctx, G, op = world
+    psi = inputs.gaussian_spinor(DIMS, 12, seed=5)
+    kind = bq.BQ_OP_MHATDAG if dagger else bq.BQ_OP_MHAT
+    fi = bq.Field(ctx, DIMS, bq.BQ_ODD, bq.BQ_F32, 12)
+    fo = bq.Field(ctx, DIMS, bq.BQ_ODD, bq.BQ_F32, 12)
+    fi.put(psi)
+    op.apply(kind, fi, fo)
+    got = fo.get()
+    sites = _sample_sites(np.random.default_rng(11 + dagger), 1, 48)
+    for c in (0, 5, 11):
+        want = orc.Mhat_sites(DIMS, U, KAPPA, CSW, psi[c], sites, t_bc=-1, mu=MU, dagger=dagger)
+        err = np.abs(got[c][sites] - want).max() / np.abs(want).max()
+        print(f"[fullsize] {'Mhat^dag' if dagger else 'Mhat'} column {c}: max rel err {err:.2e}", flush=True)
+        assert err < 1e-5, (c, err)
+
+
+@pytest.mark.timeout(600)
+def test_point_source_solve_sampled_residual(world):
+    bq, U, ctx, G, op = world
+    b = inputs.point_sources(DIMS)
+    fb = bq.Field(ctx, DIMS, bq.BQ_FULL, bq.BQ_F64, 12)
+    fx = bq.Field(ctx, DIMS, bq.BQ_FULL, bq.BQ_F64, 12)
+    fb.put(b)
+    rc, info = op.solve(fb, fx, 1e-10, system=bq.BQ_SYS_M, inner_prec=bq.BQ_F32, chunk=16)
+    assert rc == bq.BQ_OK, info
+    x = fx.get()
+    sites = _sample_sites(np.random.default_rng(13), None, 40)
+    for c in (0, 4, 11):
+        assert info[c]["converged"] and info[c]["true_rel_resid"] <= 1e-10
+        full = info[c]["full_rel_resid"]
+        assert full < 1e-8, full
+        Mx = orc.M_sites(DIMS, U, KAPPA, CSW, x[c], sites, t_bc=-1, mu=MU)
+        r = b[c][sites] - Mx
+        bnorm = np.linalg.norm(b[c])
+        worst = np.sqrt((np.abs(r) ** 2).sum(axis=(1, 2))).max() / bnorm
+        print(f"[fullsize] column {c}: full residual {full:.2e}, worst sampled site {worst:.2e}", flush=True)
+        # each site's residual is part of the global residual (up to FP64 rounding of M x)
+        assert worst <= full * 1.01 + 1e-13, (c, worst, full)
+        # the solution is not trivially zero near the source
+        assert np.abs(x[c][sites[0]]).max() > 0.5
