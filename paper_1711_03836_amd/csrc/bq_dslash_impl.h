@@ -75,21 +75,43 @@ __device__ __forceinline__ void reconstruct_add(cx<T> (&acc)[12], const cx<T> (&
 // links
 // ---------------------------------------------------------------------------
 
+// Raw storage units of N complex values of one site, as loaded (FP16: unpacked later).
+template <class P, int N>
+struct Raw {
+    static_assert(N % P::cpu == 0, "FP16 objects hold an even number of complex values");
+    typename P::unit u[N / P::cpu];
+};
+
+template <class P, int N>
+__device__ __forceinline__ void unpack_raw(const Raw<P, N>& r, cx<typename P::real> (&v)[N])
+{
+    if constexpr (P::id == PREC_F16) {
+#pragma unroll
+        for (int c = 0; c < N / 2; c++) CxIO<P16, 2>::unpack(r.u[c], v[2 * c], v[2 * c + 1]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; c++) v[c] = {r.u[c].x, r.u[c].y};
+    }
+}
+
+template <int RECON> constexpr int link_cx() { return RECON == 18 ? 9 : 6; }
+
+// link from its stored rows; with 12-real storage the third row of the SU(3) matrix is
+// conj(row0 x row1)
 template <class P, int RECON>
-__device__ __forceinline__ void load_link(const typename P::unit* __restrict__ U, int j, cx<typename P::real> (&u)[9])
+__device__ __forceinline__ void link_from_raw(const Raw<P, link_cx<RECON>()>& r, cx<typename P::real> (&u)[9])
 {
     using T = typename P::real;
     if constexpr (RECON == 18) {
-        CxIO<P, 9>::load_stream(U, j, u);
+        unpack_raw<P, 9>(r, u);
     } else {
-        cx<T> r[6];
-        CxIO<P, 6>::load_stream(U, j, r);
+        cx<T> w[6];
+        unpack_raw<P, 6>(r, w);
 #pragma unroll
-        for (int k = 0; k < 6; k++) u[k] = r[k];
-        // third row of an SU(3) matrix: conj(row0 x row1)
-        cx<T> w0 = csub(cmul(r[1], r[5]), cmul(r[2], r[4]));
-        cx<T> w1 = csub(cmul(r[2], r[3]), cmul(r[0], r[5]));
-        cx<T> w2 = csub(cmul(r[0], r[4]), cmul(r[1], r[3]));
+        for (int k = 0; k < 6; k++) u[k] = w[k];
+        const cx<T> w0 = csub(cmul(w[1], w[5]), cmul(w[2], w[4]));
+        const cx<T> w1 = csub(cmul(w[2], w[3]), cmul(w[0], w[5]));
+        const cx<T> w2 = csub(cmul(w[0], w[4]), cmul(w[1], w[3]));
         u[6] = {w0.re, -w0.im};
         u[7] = {w1.re, -w1.im};
         u[8] = {w2.re, -w2.im};
@@ -237,54 +259,130 @@ __device__ __forceinline__ void phase_end(const bool (&act)[R], cx<T> (&acc)[R][
     asm volatile("" ::: "memory");
 }
 
-template <class P, class PR, int R, int DAG, int RECON, int MU>
-__device__ __forceinline__ void hop_dir(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
-                                        cx<typename P::real> (&acc)[R][12])
+// The 8 half hops of the stencil, H = 2*mu + (0 forward, 1 backward).  A half hop's raw data
+// is its link and the R neighbour spinors.  With prefetching, the raw data of the next half hop
+// is loaded before the arithmetic of the current one, so that every wave keeps loads in flight
+// while it computes; without, each column's spinor is loaded just before its arithmetic.
+template <class P, int R, int RECON>
+struct HalfHop {
+    int jn;                                // neighbour site
+    Raw<P, link_cx<RECON>()> link;
+    Raw<P, 12> sp[R];
+    float sc[P::id == PREC_F16 ? R : 1];  // FP16 spinor scales
+};
+
+template <class P, class PR, int R, int RECON>
+__device__ __forceinline__ void hh_load_spinor(const Args<P, PR>& A, int c, int r, HalfHop<P, R, RECON>& d)
+{
+    constexpr int SU = 12 / P::cpu;
+    const typename P::unit* __restrict__ b = A.in.d + c * A.in.cstride;
+#pragma unroll
+    for (int k = 0; k < SU; k++) d.sp[r].u[k] = b[toff(d.jn, k, SU)];
+    if constexpr (P::id == PREC_F16) d.sc[r] = A.in.s[c * A.in.sstride + d.jn];
+}
+
+// neighbour index and link of half hop H: forward U_mu(x) stored at x, backward U_mu(x - mu)
+// stored at the neighbour (other parity)
+template <class P, class PR, int R, int RECON, int H>
+__device__ __forceinline__ void hh_load_link(const Args<P, PR>& A, const Site& s, HalfHop<P, R, RECON>& d)
+{
+    constexpr int MU = H >> 1;
+    constexpr bool BW = H & 1;
+    constexpr int LU = link_cx<RECON>() / P::cpu;
+    d.jn = nbr(A.g, s, MU, BW ? -1 : +1);
+    const typename P::unit* __restrict__ U = A.U[(BW ? 1 - A.parity : A.parity) * 4 + MU];
+    const int jl = BW ? d.jn : s.j;
+#pragma unroll
+    for (int k = 0; k < LU; k++) d.link.u[k] = ld_stream(&U[toff(jl, k, LU)]);
+}
+
+template <class P, class PR, int R, int RECON, int H>
+__device__ __forceinline__ void hh_load(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                        HalfHop<P, R, RECON>& d)
+{
+    hh_load_link<P, PR, R, RECON, H>(A, s, d);
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (act[r]) hh_load_spinor(A, c0 + r, r, d);
+}
+
+// forward:  acc += f U_mu(x) (1 + SF gamma_mu) psi(x + mu)
+// backward: acc += f U_mu(x - mu)^dag (1 - SF gamma_mu) psi(x - mu)
+// SF = -1 for M, +1 for the adjoint; f = e^{+-mu} (times the boundary sign) in time, else 1.
+// LOAD: load each column's spinor here, just before its arithmetic.
+template <class P, class PR, int R, int DAG, int RECON, int H, bool LOAD>
+__device__ __forceinline__ void hh_compute(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                           HalfHop<P, R, RECON>& d, cx<typename P::real> (&acc)[R][12])
 {
     using T = typename P::real;
-    constexpr int SF = DAG ? +1 : -1;  // forward term projector (1 + SF gamma_mu)
-    constexpr int SB = -SF;
+    constexpr int MU = H >> 1;
+    constexpr bool BW = H & 1;
+    constexpr int S = (DAG ? +1 : -1) * (BW ? -1 : +1);
     cx<T> u[9];
-    {   // U_mu(x) (1 + SF gamma_mu) psi(x + mu)
-        const int jf = nbr(A.g, s, MU, +1);
-        load_link<P, RECON>(A.U[A.parity * 4 + MU], s.j, u);
-        T coef = T(1);
-        if constexpr (MU == 3) coef = (s.t == A.g.L[3] - 1) ? A.ef_bc : A.ef;
+    link_from_raw<P, RECON>(d.link, u);
+    T coef = T(1);
+    if constexpr (MU == 3) {
+        if constexpr (BW) coef = (s.t == 0) ? A.eb_bc : A.eb;
+        else coef = (s.t == A.g.L[3] - 1) ? A.ef_bc : A.ef;
+    }
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            if (!act[r]) continue;
-            cx<T> p[12], h[6], y[6];
-            load_spinor(A.in, c0 + r, jf, p);
-            project<T, MU, SF>(p, h);
-            if constexpr (MU == 3) {
+    for (int r = 0; r < R; r++) {
+        if (!act[r]) continue;
+        if constexpr (LOAD) hh_load_spinor(A, c0 + r, r, d);
+        cx<T> p[12], h[6], y[6];
+        unpack_raw<P, 12>(d.sp[r], p);
+        project<T, MU, S>(p, h);
+        if constexpr (MU == 3 || P::id == PREC_F16) {
+            T k = coef;
+            if constexpr (P::id == PREC_F16) k = (MU == 3) ? k * d.sc[r] : d.sc[r];
 #pragma unroll
-                for (int k = 0; k < 6; k++) h[k] = cscale(coef, h[k]);
-            }
-            mul_U(u, h, y);
-            reconstruct_add<T, MU, SF>(acc[r], y);
+            for (int q = 0; q < 6; q++) h[q] = cscale(k, h[q]);
         }
+        if constexpr (BW) mul_Ud(u, h, y);
+        else mul_U(u, h, y);
+        reconstruct_add<T, MU, S>(acc[r], y);
+    }
+}
+
+// Loading one half hop ahead doubles the raw data held in registers; it is used where the
+// two buffers fit without spilling (one FP64 column, up to two FP32, up to three FP16).
+#ifndef BQ_PREFETCH
+#define BQ_PREFETCH 1
+#endif
+template <class P, int R>
+constexpr bool prefetch_hops()
+{
+    return BQ_PREFETCH && (P::id == PREC_F64 ? R <= 1 : (P::id == PREC_F32 ? R <= 2 : R <= 3));
+}
+
+template <class P, class PR, int R, int DAG, int RECON, int H>
+__device__ __forceinline__ void hh_step(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                        HalfHop<P, R, RECON> (&d)[2], cx<typename P::real> (&acc)[R][12])
+{
+    if constexpr (prefetch_hops<P, R>()) {
+        if constexpr (H < 7) hh_load<P, PR, R, RECON, H + 1>(A, s, act, c0, d[(H + 1) & 1]);
+        hh_compute<P, PR, R, DAG, RECON, H, false>(A, s, act, c0, d[H & 1], acc);
+    } else {
+        hh_load_link<P, PR, R, RECON, H>(A, s, d[0]);
+        hh_compute<P, PR, R, DAG, RECON, H, true>(A, s, act, c0, d[0], acc);
     }
     phase_end(act, acc);
-    {   // U_mu(x - mu)^dag (1 + SB gamma_mu) psi(x - mu)
-        const int jb = nbr(A.g, s, MU, -1);
-        load_link<P, RECON>(A.U[(1 - A.parity) * 4 + MU], jb, u);
-        T coef = T(1);
-        if constexpr (MU == 3) coef = (s.t == 0) ? A.eb_bc : A.eb;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            if (!act[r]) continue;
-            cx<T> p[12], h[6], y[6];
-            load_spinor(A.in, c0 + r, jb, p);
-            project<T, MU, SB>(p, h);
-            if constexpr (MU == 3) {
-#pragma unroll
-                for (int k = 0; k < 6; k++) h[k] = cscale(coef, h[k]);
-            }
-            mul_Ud(u, h, y);
-            reconstruct_add<T, MU, SB>(acc[r], y);
-        }
-    }
-    phase_end(act, acc);
+}
+
+template <class P, class PR, int R, int DAG, int RECON>
+__device__ __forceinline__ void hop_all(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                        cx<typename P::real> (&acc)[R][12])
+{
+    HalfHop<P, R, RECON> d[2];
+    if constexpr (prefetch_hops<P, R>()) hh_load<P, PR, R, RECON, 0>(A, s, act, c0, d[0]);
+    hh_step<P, PR, R, DAG, RECON, 0>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 1>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 2>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 3>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 4>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 5>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 6>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 7>(A, s, act, c0, d, acc);
 }
 
 // One work item: tile block `tblk` (tpb tiles) x column-group chunk `chunk` (gw groups of R
@@ -322,10 +420,7 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
 
-        hop_dir<P, PR, R, DAG, RECON, 0>(A, s, act, c0, acc);
-        hop_dir<P, PR, R, DAG, RECON, 1>(A, s, act, c0, acc);
-        hop_dir<P, PR, R, DAG, RECON, 2>(A, s, act, c0, acc);
-        hop_dir<P, PR, R, DAG, RECON, 3>(A, s, act, c0, acc);
+        hop_all<P, PR, R, DAG, RECON>(A, s, act, c0, acc);
 
         if constexpr (EPI == EPI_HOP || EPI == EPI_TINV) {
             // w = a*v + f*hop
