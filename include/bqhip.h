@@ -199,9 +199,15 @@ int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void*
 /* Stencil configuration used for a given precision and column count (set by
  * bq_autotune or explicitly; otherwise a default).  recon: 12 or 18 reals per
  * link; R: columns per thread; bs: sites per workgroup (64, 128, 256 or 512;
- * the column groups of those sites run in the same workgroup, up to 512 threads). */
-int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs);
-int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs);
+ * the column groups of those sites run in the same workgroup, up to 512 threads).
+ * march: 0, or the length of the time segments of the t-marching stencil, in
+ * which a wavefront walks `march` consecutive time planes of one tile position
+ * and keeps the backward time hop of each plane from the forward time hop two
+ * planes earlier (up to bs/64 column groups per workgroup).  It applies to
+ * lattices whose (x,y) planes hold whole 64-site tiles and whose L_t it divides;
+ * elsewhere the plain stencil runs.  Results do not depend on the configuration. */
+int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march);
+int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march);
 /* Time the candidate configurations for (op's lattice, prec, nrhs) on op and keep the fastest. */
 int bq_autotune(bq_op op, int prec, int nrhs);
 

@@ -103,8 +103,8 @@ _sig = {
                            _P(bq_solve_info)]),
     "bq_solve_stats_get": (C.c_int, [_h, _P(bq_solve_stats)]),
     "bq_time_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_int, C.c_void_p, _P(C.c_double), _P(C.c_double)]),
-    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
-    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
+    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
     "bq_server_create": (C.c_int, [_h, C.c_int, C.c_int, _P(_h)]),
     "bq_server_submit": (C.c_int, [_h, _h, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
@@ -164,12 +164,13 @@ class Context:
         return v.value
 
     def tune_get(self, prec, nrhs):
-        r, R, bs = C.c_int(), C.c_int(), C.c_int()
-        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs)))
-        return r.value, R.value, bs.value
+        """(recon, R, bs, march) of the stencil for this precision and column count."""
+        r, R, bs, m = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs), C.byref(m)))
+        return r.value, R.value, bs.value, m.value
 
-    def tune_set(self, prec, nrhs, recon, R, bs):
-        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs))
+    def tune_set(self, prec, nrhs, recon, R, bs, march=0):
+        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs, march))
 
     def close(self):
         if self.h:

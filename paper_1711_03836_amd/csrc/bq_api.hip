@@ -90,6 +90,7 @@ static int fail(int code, const char* fmt, ...)
 
 struct Tune {
     int recon, R, bs;
+    int march = 0;  // > 0: t-marching stencil with segments of this many time planes, where the lattice allows
 };
 
 struct bq_context_s {
@@ -347,6 +348,7 @@ static HopLaunch hop_base(bq_op op, int prec, const Tune& t, int dagger, int out
     L.recon = t.recon;
     L.R = std::min(t.R, std::max(ncol, 1));
     L.bs = t.bs;
+    L.march = (t.march > 0 && G->g.blocked && G->g.L[3] % t.march == 0) ? t.march : 0;
     L.dagger = dagger;
     L.g = G->g;
     L.parity = out_parity;
@@ -1530,24 +1532,26 @@ int bq_trace(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_para
     return BQ_OK;
 }
 
-int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs)
+int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march)
 {
-    if (!ctx || !recon || !R || !bs) return fail(BQ_ERR_INVALID, "NULL argument");
+    if (!ctx || !recon || !R || !bs || !march) return fail(BQ_ERR_INVALID, "NULL argument");
     Tune t = get_tune(ctx, prec, nrhs);
     *recon = t.recon;
     *R = t.R;
     *bs = t.bs;
+    *march = t.march;
     return BQ_OK;
 }
 
-int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs)
+int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march)
 {
     if (!ctx) return fail(BQ_ERR_INVALID, "NULL argument");
     const int rprec = prec == PREC_F64 ? PREC_F64 : PREC_F32;
     if (!hop_variant_exists(prec, rprec, recon, R, EPI_TV) || R > nrhs)
         return fail(BQ_ERR_INVALID, "no kernel variant for prec %d recon %d R %d (nrhs %d)", prec, recon, R, nrhs);
     if (bs != 64 && bs != 128 && bs != 256 && bs != 512) return fail(BQ_ERR_INVALID, "bs must be 64, 128, 256 or 512");
-    ctx->tune[{prec, nrhs}] = Tune{recon, R, bs};
+    if (march < 0) return fail(BQ_ERR_INVALID, "march must be >= 0");
+    ctx->tune[{prec, nrhs}] = Tune{recon, R, bs, march};
     return BQ_OK;
 }
 
@@ -1573,21 +1577,28 @@ int bq_autotune(bq_op op, int prec, int nrhs)
     };
     // pass 1: every compiled configuration, a few launches each
     std::vector<std::pair<double, Tune>> cand;
-    for (int recon : {12, 18})
-        for (int R = 1; R <= std::min(nrhs, 4); R++)
-            for (int bs : {64, 128, 256, 512}) {
-                if (!hop_variant_exists(prec, rprec, recon, R, EPI_TINV)) continue;
-                const Tune t{recon, R, bs};
-                const double ms = time_of(t, 5);
-                if (ms < 1e300) cand.push_back({ms, t});
-            }
+    // t-marching segments the lattice allows (whole tiles per (x,y) plane, segment | L_t)
+    const Geom& g = op->gauge->g;
+    std::vector<int> marches{0};
+    if (g.blocked)
+        for (int m : {4, 8, 16, 32})
+            if (g.L[3] % m == 0) marches.push_back(m);
+    for (int march : marches)
+        for (int recon : {12, 18})
+            for (int R = 1; R <= std::min(nrhs, 4); R++)
+                for (int bs : {64, 128, 256, 512}) {
+                    if (!hop_variant_exists(prec, rprec, recon, R, EPI_TINV)) continue;
+                    const Tune t{recon, R, bs, march};
+                    const double ms = time_of(t, 5);
+                    if (ms < 1e300) cand.push_back({ms, t});
+                }
     if (cand.empty()) {
         if (had_entry) ctx->tune[{prec, nrhs}] = saved; else ctx->tune.erase({prec, nrhs});
         return fail(BQ_ERR_DEVICE, "no kernel configuration could be timed");
     }
     // pass 2: the configurations within 10% of the fastest, timed again over more launches; of those
-    // within 2% of the new fastest the first in (recon, R, bs) order wins, so near-ties resolve the
-    // same way from run to run
+    // within 2% of the new fastest the first in (march, recon, R, bs) order wins, so near-ties resolve
+    // the same way from run to run
     double best = 1e300;
     for (auto& c : cand) best = std::min(best, c.first);
     std::vector<std::pair<double, Tune>> fin;

@@ -355,11 +355,11 @@ constexpr bool prefetch_hops()
     return BQ_PREFETCH && (P::id == PREC_F64 ? R <= 1 : (P::id == PREC_F32 ? R <= 2 : R <= 3));
 }
 
-template <class P, class PR, int R, int DAG, int RECON, int H>
+template <class P, class PR, int R, int DAG, int RECON, int H, bool PF = prefetch_hops<P, R>()>
 __device__ __forceinline__ void hh_step(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
                                         HalfHop<P, R, RECON> (&d)[2], cx<typename P::real> (&acc)[R][12])
 {
-    if constexpr (prefetch_hops<P, R>()) {
+    if constexpr (PF) {
         if constexpr (H < 7) hh_load<P, PR, R, RECON, H + 1>(A, s, act, c0, d[(H + 1) & 1]);
         hh_compute<P, PR, R, DAG, RECON, H, false>(A, s, act, c0, d[H & 1], acc);
     } else {
@@ -385,6 +385,132 @@ __device__ __forceinline__ void hop_all(const Args<P, PR>& A, const Site& s, con
     hh_step<P, PR, R, DAG, RECON, 7>(A, s, act, c0, d, acc);
 }
 
+// Epilogue of one tile for R columns: the linear combination and clover factor the caller
+// asked for (EPI), the store, and for EPI_TV / EPI_TVR the per-wave |.|^2 partials.  Lanes with
+// no active column pass nrm = 0 to the wave reduction.
+template <class P, class PR, int R, int EPI, bool PC>
+__device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool (&act)[R], bool any, int c0,
+                                         cx<typename P::real> (&acc)[R][12])
+{
+    using T = typename P::real;
+    using TR = typename PR::real;
+    double nrm[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) nrm[r] = 0.0;
+    if (any) {
+    if constexpr (EPI == EPI_HOP || EPI == EPI_TINV) {
+        // w = a*v + f*hop
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (!act[r]) continue;
+            const T f = colf<PC>(A, c0 + r);
+            if (A.v.d != nullptr) {
+                cx<T> v[12];
+                load_spinor(A.v, c0 + r, j, v);
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[r][k] = caxpy(f, acc[r][k], cscale(A.a, v[k]));
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[r][k] = cscale(f, acc[r][k]);
+            }
+        }
+        if constexpr (EPI == EPI_TINV) {
+#pragma unroll
+            for (int blk = 0; blk < 2; blk++) {
+                cx<T> cb[18];
+                if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (!act[r]) continue;
+                    if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
+                    cx<T> x[6];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) x[k] = acc[r][blk * 6 + k];
+                    clover_mul(cb, x, &acc[r][blk * 6]);
+                }
+                phase_end(act, acc);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (act[r]) store_spinor<P, true>(A.out, c0 + r, j, acc[r]);
+    } else if constexpr (EPI == EPI_TV) {
+        // out = C v + f*hop, assembled in place (FP16 storage needs the whole site for its scale)
+#pragma unroll
+        for (int blk = 0; blk < 2; blk++) {
+            cx<T> cb[18];
+            if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (!act[r]) continue;
+                if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
+                const T f = colf<PC>(A, c0 + r);
+                cx<T> x[6], y[6];
+                load_spinor_part(A.v, c0 + r, j, blk, x);
+                clover_mul(cb, x, y);
+#pragma unroll
+                for (int k = 0; k < 6; k++) acc[r][blk * 6 + k] = caxpy(f, acc[r][blk * 6 + k], y[k]);
+            }
+            phase_end(act, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (!act[r]) continue;
+            store_spinor(A.out, c0 + r, j, acc[r]);
+            double n = 0.0;
+#pragma unroll
+            for (int k = 0; k < 12; k++) n += (double)acc[r][k].re * acc[r][k].re + (double)acc[r][k].im * acc[r][k].im;
+            nrm[r] = n;
+        }
+    } else {
+        // w = C v + f*hop ; r_out = r_in - alpha*w, one clover block (half spinor) at a time
+        static_assert(PR::id != PREC_F16, "the residual is kept in FP32 or FP64");
+#pragma unroll
+        for (int blk = 0; blk < 2; blk++) {
+            cx<T> cb[18];
+            if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (!act[r]) continue;
+                const int c = c0 + r;
+                if constexpr (PC) load_clover_block<P>(A.cclov[c], j, blk, cb);
+                const T f = colf<PC>(A, c);
+                const TR al = A.alpha ? (TR)A.alpha[c] : TR(1);
+                cx<T> x[6], y[6];
+                load_spinor_part(A.v, c, j, blk, x);
+                clover_mul(cb, x, y);
+                cx<TR> rv[6];
+                load_spinor_part(A.rin, c, j, blk, rv);
+                typename PR::unit* rb = A.rout.d + c * A.rout.cstride;
+                double n = 0.0;
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    const cx<T> w = caxpy(f, acc[r][blk * 6 + k], y[k]);
+                    rv[k].re = fmadd(-al, (TR)w.re, rv[k].re);
+                    rv[k].im = fmadd(-al, (TR)w.im, rv[k].im);
+                    st_stream(&rb[toff(j, blk * 6 + k, 12)], {rv[k].re, rv[k].im});
+                    n += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
+                }
+                nrm[r] += n;
+            }
+            phase_end(act, acc);
+        }
+    }
+    }
+    if constexpr (EPI == EPI_TV || EPI == EPI_TVR) {
+        if (A.partial != nullptr) {
+            const int wave = j >> kTileLog;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const double t = wave_sum(nrm[r]);
+                const int c = c0 + r;
+                if ((threadIdx.x & 63) == 0 && c < A.ncol && wave < A.nwaves && col_selected(A.status, A.statmask, c))
+                    A.partial[(size_t)c * A.pstride + wave] = t;
+            }
+        }
+    }
+}
+
 // One work item: tile block `tblk` (tpb tiles) x column-group chunk `chunk` (gw groups of R
 // columns).  Wave w of the workgroup handles tile w / gw and group w % gw, so all groups of a
 // tile run side by side and share the links and clover through L1/L2.
@@ -392,7 +518,6 @@ template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
 __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chunk)
 {
     using T = typename P::real;
-    using TR = typename PR::real;
     const int w = threadIdx.x >> kTileLog;
     const int lane = threadIdx.x & (kTile - 1);
     const int gl = w % A.gw;
@@ -408,134 +533,145 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
         act[r] = j < A.g.Vh && c < A.ncol && col_selected(A.status, A.statmask, c);
         any |= act[r];
     }
-    double nrm[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) nrm[r] = 0.0;
-
+    cx<T> acc[R][12];
     if (any) {
         const Site s = site_of(A.g, A.parity, j);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
+        hop_all<P, PR, R, DAG, RECON>(A, s, act, c0, acc);
+    }
+    epilogue<P, PR, R, EPI, PC>(A, j, act, any, c0, acc);
+}
+
+// ---------------------------------------------------------------------------
+// t-marching variant (lattices whose (x,y) planes hold whole tiles)
+//
+// A wave owns one tile position (x,y block and z) and R columns and walks `seg` consecutive
+// time planes.  Lane i keeps its (x,y,z) block position, and the cb index of its site moves
+// by whole tiles from plane to plane, so the time neighbours of lane i are lane i of the same
+// tile position one plane up or down.  The site of lane i on plane t+2 is the site on plane t
+// shifted by 2 in time, so the backward time hop of plane t+2 reads the spinor that the
+// forward time hop of plane t reads: that term is computed then, from the same load, and kept
+// in registers for two planes.  Waves of neighbouring z positions march side by side, so the
+// z hops of one wave read the data its neighbours have just loaded.
+// ---------------------------------------------------------------------------
+
+// y = f U_t(x - t)^dag (1 - SF gamma_t) psi(x - t) for the output site whose backward time
+// neighbour is the half hop's neighbour site, for each active column
+template <class P, class PR, int R, int DAG, int RECON>
+__device__ __forceinline__ void t_backward(const HalfHop<P, R, RECON>& d, const cx<typename P::real> (&u)[9],
+                                           typename P::real coef, const bool (&act)[R],
+                                           cx<typename P::real> (&y)[R][6])
+{
+    using T = typename P::real;
+    constexpr int S = DAG ? -1 : +1;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (!act[r]) continue;
+        cx<T> p[12], h[6];
+        unpack_raw<P, 12>(d.sp[r], p);
+        project<T, 3, S>(p, h);
+        T k = coef;
+        if constexpr (P::id == PREC_F16) k = k * d.sc[r];
+#pragma unroll
+        for (int q = 0; q < 6; q++) h[q] = cscale(k, h[q]);
+        mul_Ud(u, h, y[r]);
+    }
+}
+
+template <class P, class PR, int R, int DAG, int RECON>
+__device__ __forceinline__ void t_link(const Args<P, PR>& A, int par, int jl, cx<typename P::real> (&u)[9])
+{
+    constexpr int LU = link_cx<RECON>() / P::cpu;
+    Raw<P, link_cx<RECON>()> raw;
+    const typename P::unit* __restrict__ U = A.U[par * 4 + 3];
+#pragma unroll
+    for (int k = 0; k < LU; k++) raw.u[k] = ld_stream(&U[toff(jl, k, LU)]);
+    link_from_raw<P, RECON>(raw, u);
+}
+
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
+__global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos, int seg, int nseg)
+{
+    using T = typename P::real;
+    constexpr int SB = DAG ? -1 : +1;  // backward projector (1 + SB gamma_t)
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int ch = lb % A.nch;
+    const int rest = lb / A.nch;
+    const int pos = rest % npos;
+    const int sg = rest / npos;
+    const int w = threadIdx.x >> kTileLog;
+    const int lane = threadIdx.x & (kTile - 1);
+    const int c0 = (ch * A.gw + w) * R;
+    const int Lt = A.g.L[3];
+    bool act[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int c = c0 + r;
+        act[r] = c < A.ncol && col_selected(A.status, A.statmask, c);
+        any |= act[r];
+    }
+    if (!any) return;  // uniform over the wave: no column of this group is selected
+    const int t0 = sg * seg;
+    auto site_at = [&](int t) { return site_of(A.g, A.parity, (pos + npos * t) * kTile + lane); };
+
+    // backward time terms of the current plane (B0) and the next (B1); the arrays are swapped
+    // after each plane so that they are indexed by constants only and stay in registers
+    cx<T> B0[R][6], B1[R][6];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int t = (t0 + q) % Lt;
+        const Site s = site_at(t);
+        HalfHop<P, R, RECON> d;
+        hh_load<P, PR, R, RECON, 7>(A, s, act, c0, d);
+        cx<T> u[9];
+        link_from_raw<P, RECON>(d.link, u);
+        t_backward<P, PR, R, DAG, RECON>(d, u, t == 0 ? A.eb_bc : A.eb, act, q == 0 ? B0 : B1);
+    }
+
+    for (int i = 0; i < seg; i++) {
+        const int t = t0 + i;
+        const Site s = site_at(t);
         cx<T> acc[R][12];
 #pragma unroll
         for (int r = 0; r < R; r++)
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
-
-        hop_all<P, PR, R, DAG, RECON>(A, s, act, c0, acc);
-
-        if constexpr (EPI == EPI_HOP || EPI == EPI_TINV) {
-            // w = a*v + f*hop
+        // the carried terms take the registers of a second prefetch buffer: no prefetching here
+        HalfHop<P, R, RECON> d[2];
+        hh_step<P, PR, R, DAG, RECON, 0, false>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 1, false>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 2, false>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 3, false>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 4, false>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 5, false>(A, s, act, c0, d, acc);
+        // forward time hop; its spinors also give the backward time term of plane t + 2
+        hh_load<P, PR, R, RECON, 6>(A, s, act, c0, d[0]);
+        hh_compute<P, PR, R, DAG, RECON, 6, false>(A, s, act, c0, d[0], acc);
+        // backward time hop of plane t, kept from plane t - 2
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                if (!act[r]) continue;
-                const T f = colf<PC>(A, c0 + r);
-                if (A.v.d != nullptr) {
-                    cx<T> v[12];
-                    load_spinor(A.v, c0 + r, j, v);
-#pragma unroll
-                    for (int k = 0; k < 12; k++) acc[r][k] = caxpy(f, acc[r][k], cscale(A.a, v[k]));
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 12; k++) acc[r][k] = cscale(f, acc[r][k]);
-                }
-            }
-            if constexpr (EPI == EPI_TINV) {
-#pragma unroll
-                for (int blk = 0; blk < 2; blk++) {
-                    cx<T> cb[18];
-                    if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
-#pragma unroll
-                    for (int r = 0; r < R; r++) {
-                        if (!act[r]) continue;
-                        if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
-                        cx<T> x[6];
-#pragma unroll
-                        for (int k = 0; k < 6; k++) x[k] = acc[r][blk * 6 + k];
-                        clover_mul(cb, x, &acc[r][blk * 6]);
-                    }
-                    phase_end(act, acc);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; r++)
-                if (act[r]) store_spinor<P, true>(A.out, c0 + r, j, acc[r]);
-        } else if constexpr (EPI == EPI_TV) {
-            // out = C v + f*hop, assembled in place (FP16 storage needs the whole site for its scale)
-#pragma unroll
-            for (int blk = 0; blk < 2; blk++) {
-                cx<T> cb[18];
-                if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    if (!act[r]) continue;
-                    if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
-                    const T f = colf<PC>(A, c0 + r);
-                    cx<T> x[6], y[6];
-                    load_spinor_part(A.v, c0 + r, j, blk, x);
-                    clover_mul(cb, x, y);
-#pragma unroll
-                    for (int k = 0; k < 6; k++) acc[r][blk * 6 + k] = caxpy(f, acc[r][blk * 6 + k], y[k]);
-                }
-                phase_end(act, acc);
-            }
-#pragma unroll
-            for (int r = 0; r < R; r++) {
-                if (!act[r]) continue;
-                store_spinor(A.out, c0 + r, j, acc[r]);
-                double n = 0.0;
-#pragma unroll
-                for (int k = 0; k < 12; k++) n += (double)acc[r][k].re * acc[r][k].re + (double)acc[r][k].im * acc[r][k].im;
-                nrm[r] = n;
-            }
-        } else {
-            // w = C v + f*hop ; r_out = r_in - alpha*w, one clover block (half spinor) at a time
-            static_assert(PR::id != PREC_F16, "the residual is kept in FP32 or FP64");
-#pragma unroll
-            for (int blk = 0; blk < 2; blk++) {
-                cx<T> cb[18];
-                if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    if (!act[r]) continue;
-                    const int c = c0 + r;
-                    if constexpr (PC) load_clover_block<P>(A.cclov[c], j, blk, cb);
-                    const T f = colf<PC>(A, c);
-                    const TR al = A.alpha ? (TR)A.alpha[c] : TR(1);
-                    cx<T> x[6], y[6];
-                    load_spinor_part(A.v, c, j, blk, x);
-                    clover_mul(cb, x, y);
-                    cx<TR> rv[6];
-                    load_spinor_part(A.rin, c, j, blk, rv);
-                    typename PR::unit* rb = A.rout.d + c * A.rout.cstride;
-                    double n = 0.0;
-#pragma unroll
-                    for (int k = 0; k < 6; k++) {
-                        const cx<T> w = caxpy(f, acc[r][blk * 6 + k], y[k]);
-                        rv[k].re = fmadd(-al, (TR)w.re, rv[k].re);
-                        rv[k].im = fmadd(-al, (TR)w.im, rv[k].im);
-                        st_stream(&rb[toff(j, blk * 6 + k, 12)], {rv[k].re, rv[k].im});
-                        n += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
-                    }
-                    nrm[r] += n;
-                }
-                phase_end(act, acc);
-            }
+        for (int r = 0; r < R; r++)
+            if (act[r]) reconstruct_add<T, 3, SB>(acc[r], B0[r]);
+        phase_end(act, acc);
+        if (i + 2 < seg) {
+            cx<T> u[9];
+            t_link<P, PR, R, DAG, RECON>(A, 1 - A.parity, d[0].jn, u);
+            t_backward<P, PR, R, DAG, RECON>(d[0], u, (t + 2) % Lt == 0 ? A.eb_bc : A.eb, act, B0);
         }
-    }
-
-    if constexpr (EPI == EPI_TV || EPI == EPI_TVR) {
-        if (A.partial != nullptr) {
-            const int wave = j >> kTileLog;
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                const double t = wave_sum(nrm[r]);
-                const int c = c0 + r;
-                if ((threadIdx.x & 63) == 0 && c < A.ncol && wave < A.nwaves && col_selected(A.status, A.statmask, c))
-                    A.partial[(size_t)c * A.pstride + wave] = t;
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const cx<T> b = B0[r][k];
+                B0[r][k] = B1[r][k];
+                B1[r][k] = b;
             }
-        }
+        epilogue<P, PR, R, EPI, PC>(A, s.j, act, true, c0, acc);
     }
 }
-
 
 // One work item per workgroup; blocks are mapped XCD-contiguously (see xcd_remap).
 template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
@@ -585,8 +721,23 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
         A.cf[c] = (T)L.cf[c];
     }
     if (L.percol && L.ncol > kMaxCols) return hipErrorInvalidValue;
-    // L.bs = sites per workgroup (a multiple of 64); at most 512 threads per workgroup
     const int G = (L.ncol + R - 1) / R;
+    if (L.march > 0) {
+        // t-marching: one tile position x column-group chunk x time segment per workgroup,
+        // at most bs / 64 column groups per workgroup
+        if (!L.g.blocked || L.g.L[3] % L.march != 0) return hipErrorInvalidValue;
+        const int gmax = std::max(1, std::min(8, L.bs / kTile));
+        A.nch = (G + gmax - 1) / gmax;
+        A.gw = (G + A.nch - 1) / A.nch;
+        A.tpb = 1;
+        const int npos = L.g.ntiles / L.g.L[3];
+        const int nseg = L.g.L[3] / L.march;
+        A.nblk = npos * nseg;
+        hipLaunchKernelGGL((k_hop_march<P, PR, R, DAG, EPI, RECON, PC>), dim3(A.nblk * A.nch), dim3(kTile * A.gw), 0,
+                           st, A, npos, L.march, nseg);
+        return hipGetLastError();
+    }
+    // L.bs = sites per workgroup (a multiple of 64); at most 512 threads per workgroup
     const int tpb = std::max(1, L.bs / kTile);
     A.tpb = tpb;
     A.gw = std::max(1, std::min(G, 512 / (tpb * kTile)));

@@ -36,6 +36,8 @@ struct HopLaunch {
     int epi = EPI_HOP;
     int R = 1;               // columns per thread
     int bs = 256;            // sites per workgroup (a multiple of 64)
+    int march = 0;           // > 0: t-marching kernel with segments of `march` time planes
+                             //      (needs whole tiles per (x,y) plane and march | L_t)
     Geom g{};
     int parity = 0;          // output parity
     int ncol = 1;

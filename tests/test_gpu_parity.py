@@ -333,3 +333,83 @@ def test_larger_lattice_k1(bq, prec, nrhs, recon, R, sb):
     for c in sorted({0, nrhs - 1}):
         want = oracle_apply(ref, bq.BQ_OP_K1, bq, psi[c])
         assert maxrel(got[c][even], want[even]) < TOL[prec]
+
+
+MARCH_KINDS = ("K1", "K1_DAG", "MHATDAG_MHAT", "M", "MDAG")
+
+
+@pytest.mark.parametrize("dims,march", [((8, 16, 8, 8), 4), ((8, 16, 8, 8), 8), ((8, 32, 4, 6), 3),
+                                        ((8, 32, 4, 6), 2)])
+@pytest.mark.parametrize("prec,recon,R,bs", [(0, 18, 1, 256), (0, 12, 2, 128), (1, 12, 3, 256), (1, 18, 1, 512),
+                                             (2, 12, 2, 128), (2, 12, 4, 64)])
+def test_march_matches_plain_and_oracle(bq, dims, march, prec, recon, R, bs):
+    """The t-marching stencil performs each site's arithmetic in the plain stencil's order, so every
+    operator kind is bitwise the plain result; both match the oracle.  A solve with it converges to
+    bitwise the plain solve's solution."""
+    U = inputs.gauge_field(dims, 0.3, seed=19)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.124, 1.5, 0.1)
+    ref = orc.Operator(dims, U, 0.124, 1.5, mu=0.1)
+    nrhs = 12 if R > 1 else 3
+    psi = inputs.gaussian_spinor(dims, nrhs, seed=31)
+    for name in MARCH_KINDS:
+        kind = getattr(bq, "BQ_OP_" + name)
+        si, so = bq.OP_SUBSETS[kind]
+        out = {}
+        for m in (0, march):
+            ctx.tune_set(prec, nrhs, recon, R, bs, m)
+            assert ctx.tune_get(prec, nrhs) == (recon, R, bs, m)
+            fi = bq.Field(ctx, dims, si, prec, nrhs)
+            fo = bq.Field(ctx, dims, so, prec, nrhs)
+            fi.put(psi)
+            op.apply(kind, fi, fo)
+            out[m] = fo.get()
+        assert np.array_equal(out[0], out[march]), name
+        mask = {bq.BQ_EVEN: ref.parity == 0, bq.BQ_ODD: ref.parity == 1, bq.BQ_FULL: np.ones(ref.V, bool)}[so]
+        for c in sorted({0, nrhs - 1}):
+            want = oracle_apply(ref, kind, bq, psi[c])
+            assert maxrel(out[march][c][mask], want[mask]) < TOL[prec], (name, c)
+    b = inputs.gaussian_spinor(dims, 2, seed=37)
+    xs = {}
+    for m in (0, march):
+        ctx.tune_set(prec, 2, recon, min(R, 2), bs, m)
+        x, info = _solve(bq, op, dims, b, bq.BQ_SYS_M, prec, 1e-10, 2)
+        assert all(c["converged"] for c in info)
+        xs[m] = x
+    assert np.array_equal(xs[0], xs[march])
+    for c in range(2):
+        assert np.linalg.norm(b[c] - ref.M(xs[march][c])) / np.linalg.norm(b[c]) < 1e-7
+
+
+@pytest.mark.parametrize("prec,recon,R,bs,march", [(1, 12, 3, 256, 16), (1, 12, 1, 512, 8), (0, 18, 1, 256, 32),
+                                                   (2, 12, 2, 128, 4)])
+def test_march_larger_lattice_bitwise(bq, prec, recon, R, bs, march):
+    """16^3x32 (16 tiles per (x,y) plane): t-marching K1, K2-type and residual-update kernels (through
+    Mhat^dag Mhat and a solve) are bitwise the plain stencil's."""
+    dims = (16, 16, 16, 32)
+    U = inputs.gauge_field(dims, 0.2, seed=43)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.125, 1.7, 0.05)
+    nrhs = 12
+    psi = inputs.gaussian_spinor(dims, nrhs, seed=47)
+    for name in ("K1", "MHATDAG_MHAT"):
+        kind = getattr(bq, "BQ_OP_" + name)
+        si, so = bq.OP_SUBSETS[kind]
+        out = {}
+        for m in (0, march):
+            ctx.tune_set(prec, nrhs, recon, R, bs, m)
+            fi = bq.Field(ctx, dims, si, prec, nrhs)
+            fo = bq.Field(ctx, dims, so, prec, nrhs)
+            fi.put(psi)
+            op.apply(kind, fi, fo)
+            out[m] = fo.get()
+        assert np.array_equal(out[0], out[march]), name
+    xs = {}
+    for m in (0, march):
+        ctx.tune_set(prec, nrhs, recon, R, bs, m)
+        x, info = _solve(bq, op, dims, psi, bq.BQ_SYS_M, prec, 1e-9, nrhs)
+        assert all(c["converged"] for c in info)
+        xs[m] = x
+    assert np.array_equal(xs[0], xs[march])
