@@ -71,6 +71,32 @@ __device__ __forceinline__ void reconstruct_add(cx<T> (&acc)[12], const cx<T> (&
     }
 }
 
+// acc += k (1 + S gamma_mu) psi, given the unscaled half spinor h (the scale folded into FMAs)
+template <typename T, int MU, int S>
+__device__ __forceinline__ void reconstruct_add_k(cx<T> (&acc)[12], const cx<T> (&h)[6], T k)
+{
+    auto fma_c = [](T kk, cx<T> v, cx<T> a) { return cx<T>{fmadd(kk, v.re, a.re), fmadd(kk, v.im, a.im)}; };
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<T> h0 = h[c], h1 = h[3 + c];
+        acc[c] = fma_c(k, h0, acc[c]);
+        acc[3 + c] = fma_c(k, h1, acc[3 + c]);
+        if constexpr (MU == 0) {          // rows 2,3 = -S i h1, -S i h0
+            acc[6 + c] = fma_c(-k, pmi<T, S>(h1), acc[6 + c]);
+            acc[9 + c] = fma_c(-k, pmi<T, S>(h0), acc[9 + c]);
+        } else if constexpr (MU == 1) {   // rows 2,3 = S h1, -S h0
+            acc[6 + c] = fma_c(S > 0 ? k : -k, h1, acc[6 + c]);
+            acc[9 + c] = fma_c(S > 0 ? -k : k, h0, acc[9 + c]);
+        } else if constexpr (MU == 2) {   // rows 2,3 = -S i h0, S i h1
+            acc[6 + c] = fma_c(-k, pmi<T, S>(h0), acc[6 + c]);
+            acc[9 + c] = fma_c(k, pmi<T, S>(h1), acc[9 + c]);
+        } else {                          // rows 2,3 = S h0, S h1
+            acc[6 + c] = fma_c(S > 0 ? k : -k, h0, acc[6 + c]);
+            acc[9 + c] = fma_c(S > 0 ? k : -k, h1, acc[9 + c]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // links
 // ---------------------------------------------------------------------------
@@ -145,6 +171,40 @@ __device__ __forceinline__ void mul_Ud(const cx<T> (&u)[9], const cx<T> (&h)[6],
             s = cmacc(s, u[2 * 3 + a], h[k * 3 + 2]);
             y[k * 3 + a] = s;
         }
+}
+
+// ---------------------------------------------------------------------------
+// one hop product y = k U (1 + S gamma_mu) psi (BW: U^dag), from raw storage: unpack,
+// project, scale the half spinor, multiply.  FP16 storage is unpacked to FP32 and all
+// arithmetic is FP32; its factor k (site scale, times e^{+-mu} in time) is folded into the
+// FMAs of the reconstruction by the caller instead (SCALE = false).
+// ---------------------------------------------------------------------------
+
+template <class P, int RECON, bool BW>
+struct PLink {
+    cx<typename P::real> u[9];
+};
+
+template <class P, int RECON, bool BW>
+__device__ __forceinline__ void prep_link(const Raw<P, link_cx<RECON>()>& raw, PLink<P, RECON, BW>& L)
+{
+    link_from_raw<P, RECON>(raw, L.u);
+}
+
+template <class P, int RECON, int MU, int S, bool BW, bool SCALE>
+__device__ __forceinline__ void hop_product(const PLink<P, RECON, BW>& L, const Raw<P, 12>& sp,
+                                            typename P::real k, cx<typename P::real> (&y)[6])
+{
+    using T = typename P::real;
+    cx<T> p[12], h[6];
+    unpack_raw<P, 12>(sp, p);
+    project<T, MU, S>(p, h);
+    if constexpr (SCALE) {
+#pragma unroll
+        for (int q = 0; q < 6; q++) h[q] = cscale(k, h[q]);
+    }
+    if constexpr (BW) mul_Ud(L.u, h, y);
+    else mul_U(L.u, h, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -318,8 +378,8 @@ __device__ __forceinline__ void hh_compute(const Args<P, PR>& A, const Site& s, 
     constexpr int MU = H >> 1;
     constexpr bool BW = H & 1;
     constexpr int S = (DAG ? +1 : -1) * (BW ? -1 : +1);
-    cx<T> u[9];
-    link_from_raw<P, RECON>(d.link, u);
+    PLink<P, RECON, BW> L;
+    prep_link<P, RECON, BW>(d.link, L);
     T coef = T(1);
     if constexpr (MU == 3) {
         if constexpr (BW) coef = (s.t == 0) ? A.eb_bc : A.eb;
@@ -329,18 +389,14 @@ __device__ __forceinline__ void hh_compute(const Args<P, PR>& A, const Site& s, 
     for (int r = 0; r < R; r++) {
         if (!act[r]) continue;
         if constexpr (LOAD) hh_load_spinor(A, c0 + r, r, d);
-        cx<T> p[12], h[6], y[6];
-        unpack_raw<P, 12>(d.sp[r], p);
-        project<T, MU, S>(p, h);
-        if constexpr (MU == 3 || P::id == PREC_F16) {
-            T k = coef;
-            if constexpr (P::id == PREC_F16) k = (MU == 3) ? k * d.sc[r] : d.sc[r];
-#pragma unroll
-            for (int q = 0; q < 6; q++) h[q] = cscale(k, h[q]);
+        cx<T> y[6];
+        if constexpr (P::id == PREC_F16) {
+            hop_product<P, RECON, MU, S, BW, false>(L, d.sp[r], T(1), y);
+            reconstruct_add_k<T, MU, S>(acc[r], y, (MU == 3) ? coef * d.sc[r] : d.sc[r]);
+        } else {
+            hop_product<P, RECON, MU, S, BW, MU == 3>(L, d.sp[r], coef, y);
+            reconstruct_add<T, MU, S>(acc[r], y);
         }
-        if constexpr (BW) mul_Ud(u, h, y);
-        else mul_U(u, h, y);
-        reconstruct_add<T, MU, S>(acc[r], y);
     }
 }
 
@@ -560,36 +616,34 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
 
 // y = f U_t(x - t)^dag (1 - SF gamma_t) psi(x - t) for the output site whose backward time
 // neighbour is the half hop's neighbour site, for each active column
+// (FP16: y unscaled, its factor in ky)
 template <class P, class PR, int R, int DAG, int RECON>
-__device__ __forceinline__ void t_backward(const HalfHop<P, R, RECON>& d, const cx<typename P::real> (&u)[9],
+__device__ __forceinline__ void t_backward(const HalfHop<P, R, RECON>& d, const PLink<P, RECON, true>& L,
                                            typename P::real coef, const bool (&act)[R],
-                                           cx<typename P::real> (&y)[R][6])
+                                           cx<typename P::real> (&y)[R][6], typename P::real (&ky)[R])
 {
-    using T = typename P::real;
     constexpr int S = DAG ? -1 : +1;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         if (!act[r]) continue;
-        cx<T> p[12], h[6];
-        unpack_raw<P, 12>(d.sp[r], p);
-        project<T, 3, S>(p, h);
-        T k = coef;
-        if constexpr (P::id == PREC_F16) k = k * d.sc[r];
-#pragma unroll
-        for (int q = 0; q < 6; q++) h[q] = cscale(k, h[q]);
-        mul_Ud(u, h, y[r]);
+        if constexpr (P::id == PREC_F16) {
+            hop_product<P, RECON, 3, S, true, false>(L, d.sp[r], 1.0f, y[r]);
+            ky[r] = coef * d.sc[r];
+        } else {
+            hop_product<P, RECON, 3, S, true, true>(L, d.sp[r], coef, y[r]);
+        }
     }
 }
 
 template <class P, class PR, int R, int DAG, int RECON>
-__device__ __forceinline__ void t_link(const Args<P, PR>& A, int par, int jl, cx<typename P::real> (&u)[9])
+__device__ __forceinline__ void t_link(const Args<P, PR>& A, int par, int jl, PLink<P, RECON, true>& L)
 {
     constexpr int LU = link_cx<RECON>() / P::cpu;
     Raw<P, link_cx<RECON>()> raw;
     const typename P::unit* __restrict__ U = A.U[par * 4 + 3];
 #pragma unroll
     for (int k = 0; k < LU; k++) raw.u[k] = ld_stream(&U[toff(jl, k, LU)]);
-    link_from_raw<P, RECON>(raw, u);
+    prep_link<P, RECON, true>(raw, L);
 }
 
 template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
@@ -621,15 +675,16 @@ __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos
     // backward time terms of the current plane (B0) and the next (B1); the arrays are swapped
     // after each plane so that they are indexed by constants only and stay in registers
     cx<T> B0[R][6], B1[R][6];
+    T K0[R], K1[R];  // FP16: factors of B0, B1
 #pragma unroll
     for (int q = 0; q < 2; q++) {
         const int t = (t0 + q) % Lt;
         const Site s = site_at(t);
         HalfHop<P, R, RECON> d;
         hh_load<P, PR, R, RECON, 7>(A, s, act, c0, d);
-        cx<T> u[9];
-        link_from_raw<P, RECON>(d.link, u);
-        t_backward<P, PR, R, DAG, RECON>(d, u, t == 0 ? A.eb_bc : A.eb, act, q == 0 ? B0 : B1);
+        PLink<P, RECON, true> L;
+        prep_link<P, RECON, true>(d.link, L);
+        t_backward<P, PR, R, DAG, RECON>(d, L, t == 0 ? A.eb_bc : A.eb, act, q == 0 ? B0 : B1, q == 0 ? K0 : K1);
     }
 
     for (int i = 0; i < seg; i++) {
@@ -653,22 +708,29 @@ __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos
         hh_compute<P, PR, R, DAG, RECON, 6, false>(A, s, act, c0, d[0], acc);
         // backward time hop of plane t, kept from plane t - 2
 #pragma unroll
-        for (int r = 0; r < R; r++)
-            if (act[r]) reconstruct_add<T, 3, SB>(acc[r], B0[r]);
+        for (int r = 0; r < R; r++) {
+            if (!act[r]) continue;
+            if constexpr (P::id == PREC_F16) reconstruct_add_k<T, 3, SB>(acc[r], B0[r], K0[r]);
+            else reconstruct_add<T, 3, SB>(acc[r], B0[r]);
+        }
         phase_end(act, acc);
         if (i + 2 < seg) {
-            cx<T> u[9];
-            t_link<P, PR, R, DAG, RECON>(A, 1 - A.parity, d[0].jn, u);
-            t_backward<P, PR, R, DAG, RECON>(d[0], u, (t + 2) % Lt == 0 ? A.eb_bc : A.eb, act, B0);
+            PLink<P, RECON, true> L;
+            t_link<P, PR, R, DAG, RECON>(A, 1 - A.parity, d[0].jn, L);
+            t_backward<P, PR, R, DAG, RECON>(d[0], L, (t + 2) % Lt == 0 ? A.eb_bc : A.eb, act, B0, K0);
         }
 #pragma unroll
-        for (int r = 0; r < R; r++)
+        for (int r = 0; r < R; r++) {
 #pragma unroll
             for (int k = 0; k < 6; k++) {
                 const cx<T> b = B0[r][k];
                 B0[r][k] = B1[r][k];
                 B1[r][k] = b;
             }
+            const T kk = K0[r];
+            K0[r] = K1[r];
+            K1[r] = kk;
+        }
         epilogue<P, PR, R, EPI, PC>(A, s.j, act, true, c0, acc);
     }
 }

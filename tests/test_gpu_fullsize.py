@@ -92,3 +92,30 @@ def test_point_source_solve_sampled_residual(world):
         assert worst <= full * 1.01 + 1e-13, (c, worst, full)
         # the solution is not trivially zero near the source
         assert np.abs(x[c][sites[0]]).max() > 0.5
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("inner", [0, 1, 2])
+def test_single_source_16x32_oracle_residual(inner):
+    """16^3x32, U = exp(0.2 i H), kappa 0.125, c_SW 1.7, one Gaussian source, tol 1e-10 through the
+    Schur system with FP64, FP32-inner and FP16-inner CG: the oracle recomputes b - M x on the whole
+    lattice from the GPU solution and agrees with the full-system residual the library reports."""
+    from paper_1711_03836_amd import bqhip as bq
+    dims = (16, 16, 16, 32)
+    U = inputs.gauge_field(dims, 0.2, seed=1711)
+    b = inputs.gaussian_spinor(dims, 1, seed=3836)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.125, 1.7, 0.0)
+    fb = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, 1)
+    fx = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, 1)
+    fb.put(b)
+    rc, info = op.solve(fb, fx, 1e-10, system=bq.BQ_SYS_M, inner_prec=inner, chunk=16)
+    assert rc == bq.BQ_OK and info[0]["converged"] and info[0]["true_rel_resid"] <= 1e-10
+    x = fx.get()[0]
+    ref = orc.Operator(dims, U, 0.125, 1.7)
+    rel = np.linalg.norm(b[0] - ref.M(x)) / np.linalg.norm(b[0])
+    print(f"[single16] inner {inner}: {info[0]['iters']} iterations, oracle residual {rel:.3e}, "
+          f"reported {info[0]['full_rel_resid']:.3e}", flush=True)
+    assert abs(rel - info[0]["full_rel_resid"]) <= 0.01 * rel + 1e-15
+    assert rel < 1e-8
