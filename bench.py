@@ -13,7 +13,9 @@ value = algorithmic HBM bytes the library accounts for the K timed solves
 (every kernel's inputs read once, outputs written once) / wall time, GB/s.
 The JSON line also carries the roofline of the EO-clover Dslash kernel
 K1 = T_ee^-1 D_eo (HIP events on the kernel's stream), the FP64-CG vs mixed
-time-to-solution on the same GPU, and the CPU oracle timed on a bounded sample.
+time-to-solution on the same GPU for both inner precisions, single-column K1
+figures, a short continuous-batching serving run (p50/p99), and the CPU oracle
+timed on a bounded sample.
 """
 import argparse
 import json
@@ -47,6 +49,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--other-inner", type=int, default=1, help="also time the other inner precision (1/0)")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests of the short serving run (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8)
     args = ap.parse_args()
@@ -131,6 +134,22 @@ def main():
         log(f"[bench] FP64 CG {mixed_vs['fp64_ms']:.1f} ms vs mixed {mixed_vs['mixed_ms']:.1f} ms "
             f"(x{mixed_vs['speedup']:.2f})")
 
+    # the other inner precision on the same sources (FP16 storage with FP32 arithmetic, or FP32)
+    other = None
+    if not args.no_fp64 and args.other_inner:
+        oname = "f16" if args.inner == "f32" else "f32"
+        op.autotune(PREC_NAMES[oname], nrhs)
+        solve(PREC_NAMES[oname])
+        info_o, st_o = solve(PREC_NAMES[oname])
+        assert all(c["converged"] for c in info_o), info_o
+        other = {"inner_prec": oname, "ms": st_o["seconds"] * 1e3, "speedup_vs_fp64": st64["seconds"] / st_o["seconds"],
+                 "iters": max(c["iters"] for c in info_o),
+                 "reliable_updates": max(c["reliable_updates"] for c in info_o),
+                 "true_rel_resid": max(c["true_rel_resid"] for c in info_o),
+                 "full_rel_resid": max(c["full_rel_resid"] for c in info_o),
+                 "tune": ctx.tune_get(PREC_NAMES[oname], nrhs)}
+        log(f"[bench] {oname} inner: {other['ms']:.1f} ms (x{other['speedup_vs_fp64']:.2f} vs FP64)")
+
     # roofline of the EO-clover Dslash K1 = T_ee^-1 D_eo, HIP events on the stream it runs on
     dslash = {}
     roof = None
@@ -145,6 +164,18 @@ def main():
         dslash[name] = {"k1_ms": ms, "k1_bytes": by, "k1_gbs": by / ms / 1e6, "k1_frac": by / ms / 1e6 / HBM_PEAK_GBS,
                         "mdagm_ms": ms2, "mdagm_gbs": by2 / ms2 / 1e6, "tune": ctx.tune_get(prec, nrhs)}
         log(f"[bench] K1 {name} x{nrhs}: {ms:.3f} ms, {by/ms/1e6:.0f} GB/s; Mhat^dag Mhat {by2/ms2/1e6:.0f} GB/s")
+    # single-column K1 in each precision (autotuned), same lattice and operator
+    single = {}
+    for name, prec in (("f64", 0), ("f32", 1), ("f16", 2)):
+        op.autotune(prec, 1)
+        fo = bq.Field(ctx, dims, bq.BQ_ODD, prec, 1)
+        fe = bq.Field(ctx, dims, bq.BQ_EVEN, prec, 1)
+        fo.put(inputs.gaussian_spinor(dims, 1, seed=7))
+        ms, by = op.time_apply(bq.BQ_OP_K1, fo, fe, reps=args.kernel_reps, stream=stream)
+        single[name] = {"k1_ms": ms, "k1_bytes": by, "k1_gbs": by / ms / 1e6, "k1_frac": by / ms / 1e6 / HBM_PEAK_GBS,
+                        "tune": ctx.tune_get(prec, 1)}
+        log(f"[bench] K1 {name} x1: {ms:.3f} ms, {by/ms/1e6:.0f} GB/s ({by/ms/1e6/HBM_PEAK_GBS:.1%} of 8 TB/s)")
+
     k = dslash[args.inner]
     traffic, traffic_note = measured_traffic(dims, args.inner, nrhs, k["tune"])
     roof = {"bound": "hbm", "achieved": k["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -168,7 +199,8 @@ def main():
                                f"mu={mu}, kappa={kappa}, c_SW={csw}, U=exp({eps} i H), tol {tol:g}, "
                                f"{args.inner} inner + f64 reliable updates",
                    "lattice": list(dims), "nrhs": nrhs, "plaquette": plaq},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "dslash": dslash, "serving": serving,
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "other_inner": other, "dslash": dslash,
+        "dslash_single_rhs": single, "serving": serving,
         "solve": {"true_rel_resid": worst_true, "full_rel_resid": worst_full,
                   "iters": max(c["iters"] for c in last_info),
                   "reliable_updates": max(c["reliable_updates"] for c in last_info),

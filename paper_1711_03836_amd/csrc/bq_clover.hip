@@ -89,7 +89,7 @@ __device__ __forceinline__ M3 link_at(const Geom& g, const double2* const* U, co
     M3 m;
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-        double2 t = b[toff(j, k, 9)];
+        double2 t = at(b, j, k, 9);
         m.m[k] = {t.x, t.y};
     }
     return m;
@@ -166,22 +166,22 @@ struct H6 {
 __device__ __forceinline__ void pack_store(double2* T, int j, int blk, const H6& A)
 {
     if (T == nullptr) return;
-    T[toff(j, blk * 18 + 0, 36)] = make_double2(A.a[0].re, A.a[7].re);
-    T[toff(j, blk * 18 + 1, 36)] = make_double2(A.a[14].re, A.a[21].re);
-    T[toff(j, blk * 18 + 2, 36)] = make_double2(A.a[28].re, A.a[35].re);
+    at(T, j, blk * 18 + 0, 36) = make_double2(A.a[0].re, A.a[7].re);
+    at(T, j, blk * 18 + 1, 36) = make_double2(A.a[14].re, A.a[21].re);
+    at(T, j, blk * 18 + 2, 36) = make_double2(A.a[28].re, A.a[35].re);
 #pragma unroll
     for (int i = 1; i < 6; i++)
 #pragma unroll
         for (int k = 0; k < i; k++) {
             const c64 v = A.a[i * 6 + k];
-            T[toff(j, blk * 18 + 3 + i * (i - 1) / 2 + k, 36)] = make_double2(v.re, v.im);
+            at(T, j, blk * 18 + 3 + i * (i - 1) / 2 + k, 36) = make_double2(v.re, v.im);
         }
 }
 
 __device__ __forceinline__ H6 pack_load(const double2* T, int j, int blk)
 {
     H6 A;
-    double2 d0 = T[toff(j, blk * 18 + 0, 36)], d1 = T[toff(j, blk * 18 + 1, 36)], d2 = T[toff(j, blk * 18 + 2, 36)];
+    double2 d0 = at(T, j, blk * 18 + 0, 36), d1 = at(T, j, blk * 18 + 1, 36), d2 = at(T, j, blk * 18 + 2, 36);
     const double d[6] = {d0.x, d0.y, d1.x, d1.y, d2.x, d2.y};
 #pragma unroll
     for (int i = 0; i < 6; i++) A.a[i * 6 + i] = {d[i], 0.0};
@@ -189,7 +189,7 @@ __device__ __forceinline__ H6 pack_load(const double2* T, int j, int blk)
     for (int i = 1; i < 6; i++)
 #pragma unroll
         for (int k = 0; k < i; k++) {
-            double2 t = T[toff(j, blk * 18 + 3 + i * (i - 1) / 2 + k, 36)];
+            double2 t = at(T, j, blk * 18 + 3 + i * (i - 1) / 2 + k, 36);
             A.a[i * 6 + k] = {t.x, t.y};
             A.a[k * 6 + i] = {t.x, -t.y};
         }
@@ -359,11 +359,11 @@ __global__ void k_clover_apply(const Geom g, const typename P::unit* C0, SpinorP
         cx<T> cb[18];
         if constexpr (P::id == PREC_F16) {
 #pragma unroll
-            for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(C[toff(j, blk * 9 + u, 18)], cb[2 * u], cb[2 * u + 1]);
+            for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(at(C, j, blk * 9 + u, 18), cb[2 * u], cb[2 * u + 1]);
         } else {
 #pragma unroll
             for (int k = 0; k < 18; k++) {
-                auto t = C[toff(j, blk * 18 + k, 36)];
+                auto t = at(C, j, blk * 18 + k, 36);
                 cb[k] = {t.x, t.y};
             }
         }
@@ -382,12 +382,15 @@ __global__ void k_clover_apply(const Geom g, const typename P::unit* C0, SpinorP
     store_spinor(out, c, j, y);
 }
 
-__global__ void k_clover_convert32(const double2* src, float2* dst, size_t n)
+// FP64 -> FP32 clover, one storage unit of one site per thread (the two precisions' tiles
+// order their units differently)
+__global__ void k_clover_convert32(const double2* src, float2* dst, int Vh)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 t = src[i];
-    dst[i] = make_float2((float)t.x, (float)t.y);
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = blockIdx.y;
+    if (j >= Vh) return;
+    const double2 t = at(src, j, u, 36);
+    at(dst, j, u, 36) = make_float2((float)t.x, (float)t.y);
 }
 
 // FP64 packed clover (36 complex/site) -> FP16 (18 units of 2 complex/site)
@@ -396,8 +399,8 @@ __global__ void k_clover_convert16(const double2* src, uint2* dst, int Vh)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int u = blockIdx.y;  // 0..17
     if (j >= Vh) return;
-    double2 a = src[toff(j, 2 * u, 36)], b = src[toff(j, 2 * u + 1, 36)];
-    dst[toff(j, u, 18)] = CxIO<P16, 2>::pack(cx<float>{(float)a.x, (float)a.y}, cx<float>{(float)b.x, (float)b.y});
+    double2 a = at(src, j, 2 * u, 36), b = at(src, j, 2 * u + 1, 36);
+    at(dst, j, u, 18) = CxIO<P16, 2>::pack(cx<float>{(float)a.x, (float)a.y}, cx<float>{(float)b.x, (float)b.y});
 }
 
 // sum over the 6 planes of Re tr U_{mu nu}(x) / 3, one FP64 partial per wavefront
@@ -500,8 +503,7 @@ hipError_t launch_clover_convert(int prec, const double2* src, void* dst, int Vh
     const int bs = 256;
     const int Vp = pad_sites(Vh);
     if (prec == PREC_F32) {
-        const size_t n = (size_t)Vp * 36;
-        hipLaunchKernelGGL(k_clover_convert32, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, src, (float2*)dst, n);
+        hipLaunchKernelGGL(k_clover_convert32, dim3((Vp + bs - 1) / bs, 36), dim3(bs), 0, st, src, (float2*)dst, Vp);
     } else if (prec == PREC_F16) {
         hipLaunchKernelGGL(k_clover_convert16, dim3((Vh + bs - 1) / bs, 18), dim3(bs), 0, st, src, (uint2*)dst, Vh);
     } else {

@@ -4,11 +4,16 @@
 //
 // Layout (all fields live on one checkerboard = one parity, Vh = V/2 sites):
 //   a site-tiled structure of arrays.  Sites are grouped in tiles of 64 (one
-//   wavefront); inside a tile each storage unit c of an object occupies 64
-//   consecutive slots, so lane l of a wave reading unit c of its own site reads
-//   slot l of a 64-wide contiguous run.  offset(j, c) = ((j/64)*nunits + c)*64 + j%64.
-//   This is the paper's "SIMD vector as the smallest structure" layout with the
-//   wavefront as the vector.
+//   wavefront).  Inside a tile, 16-byte storage units (FP64) occupy 64
+//   consecutive slots per unit: lane l reads slot l of a contiguous run,
+//     offset(j, c) = ((j/64)*nunits + c)*64 + j%64.
+//   Units of 8 bytes (FP32, FP16) are stored in pairs, two units of one site
+//   side by side, so that a lane reads both with one 16-byte load:
+//     offset(j, c) = ((j/64)*nunits + c - c%2)*64 + 2*(j%64) + c%2,
+//   except that the last unit of an object with an odd unit count is stored
+//   alone, as for 16-byte units.  With either rule a tile of an object covers
+//   nunits*64 consecutive units.  The innermost index runs over the sites of a
+//   wavefront, as the paper's SIMD layout puts a vector of sites innermost (5.1).
 //
 // Storage units per precision:
 //   FP64: one complex per unit (double2, 16 B)
@@ -26,9 +31,28 @@ namespace bq {
 constexpr int kTileLog = 6;
 constexpr int kTile = 1 << kTileLog;
 
+// offset, in units of U, of unit c (of nunits) of site j
+template <class U>
 __host__ __device__ __forceinline__ size_t toff(int j, int c, int nunits)
 {
-    return ((size_t)(j >> kTileLog) * nunits + c) * kTile + (j & (kTile - 1));
+    const size_t tile = (size_t)(j >> kTileLog) * nunits * kTile;
+    const int lane = j & (kTile - 1);
+    if constexpr (sizeof(U) > 8) {
+        return tile + (size_t)c * kTile + lane;
+    } else {
+        if ((nunits & 1) && c == nunits - 1) return tile + (size_t)c * kTile + lane;
+        return tile + (size_t)(c & ~1) * kTile + 2 * lane + (c & 1);
+    }
+}
+template <class U>
+__host__ __device__ __forceinline__ U& at(U* p, int j, int c, int nunits)
+{
+    return p[toff<U>(j, c, nunits)];
+}
+template <class U>
+__host__ __device__ __forceinline__ const U& at(const U* p, int j, int c, int nunits)
+{
+    return p[toff<U>(j, c, nunits)];
 }
 
 __host__ __device__ __forceinline__ int pad_sites(int n) { return (n + kTile - 1) & ~(kTile - 1); }
@@ -181,27 +205,27 @@ template <int N> struct CxIO<P64, N> {
     __device__ __forceinline__ static void load(const double2* __restrict__ b, int j, cx<double> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) { double2 t = b[toff(j, c, N)]; v[c] = {t.x, t.y}; }
+        for (int c = 0; c < N; c++) { double2 t = at(b, j, c, N); v[c] = {t.x, t.y}; }
     }
     __device__ __forceinline__ static void load_cached(const double2* __restrict__ b, int j, cx<double> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) { double2 t = b[toff(j, c, N)]; v[c] = {t.x, t.y}; }
+        for (int c = 0; c < N; c++) { double2 t = at(b, j, c, N); v[c] = {t.x, t.y}; }
     }
     __device__ __forceinline__ static void store(double2* __restrict__ b, int j, const cx<double> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) b[toff(j, c, N)] = make_double2(v[c].re, v[c].im);
+        for (int c = 0; c < N; c++) at(b, j, c, N) = make_double2(v[c].re, v[c].im);
     }
     __device__ __forceinline__ static void load_stream(const double2* __restrict__ b, int j, cx<double> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) { double2 t = ld_stream(&b[toff(j, c, N)]); v[c] = {t.x, t.y}; }
+        for (int c = 0; c < N; c++) { double2 t = ld_stream(&at(b, j, c, N)); v[c] = {t.x, t.y}; }
     }
     __device__ __forceinline__ static void store_stream(double2* __restrict__ b, int j, const cx<double> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) st_stream(&b[toff(j, c, N)], make_double2(v[c].re, v[c].im));
+        for (int c = 0; c < N; c++) st_stream(&at(b, j, c, N), make_double2(v[c].re, v[c].im));
     }
 };
 
@@ -210,27 +234,27 @@ template <int N> struct CxIO<P32, N> {
     __device__ __forceinline__ static void load(const float2* __restrict__ b, int j, cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) { float2 t = b[toff(j, c, N)]; v[c] = {t.x, t.y}; }
+        for (int c = 0; c < N; c++) { float2 t = at(b, j, c, N); v[c] = {t.x, t.y}; }
     }
     __device__ __forceinline__ static void load_cached(const float2* __restrict__ b, int j, cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) { float2 t = b[toff(j, c, N)]; v[c] = {t.x, t.y}; }
+        for (int c = 0; c < N; c++) { float2 t = at(b, j, c, N); v[c] = {t.x, t.y}; }
     }
     __device__ __forceinline__ static void store(float2* __restrict__ b, int j, const cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) b[toff(j, c, N)] = make_float2(v[c].re, v[c].im);
+        for (int c = 0; c < N; c++) at(b, j, c, N) = make_float2(v[c].re, v[c].im);
     }
     __device__ __forceinline__ static void load_stream(const float2* __restrict__ b, int j, cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) { float2 t = ld_stream(&b[toff(j, c, N)]); v[c] = {t.x, t.y}; }
+        for (int c = 0; c < N; c++) { float2 t = ld_stream(&at(b, j, c, N)); v[c] = {t.x, t.y}; }
     }
     __device__ __forceinline__ static void store_stream(float2* __restrict__ b, int j, const cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N; c++) st_stream(&b[toff(j, c, N)], make_float2(v[c].re, v[c].im));
+        for (int c = 0; c < N; c++) st_stream(&at(b, j, c, N), make_float2(v[c].re, v[c].im));
     }
 };
 
@@ -249,27 +273,27 @@ template <int N> struct CxIO<P16, N> {
     __device__ __forceinline__ static void load(const uint2* __restrict__ b, int j, cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N / 2; c++) unpack(b[toff(j, c, N / 2)], v[2 * c], v[2 * c + 1]);
+        for (int c = 0; c < N / 2; c++) unpack(at(b, j, c, N / 2), v[2 * c], v[2 * c + 1]);
     }
     __device__ __forceinline__ static void load_cached(const uint2* __restrict__ b, int j, cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N / 2; c++) unpack(b[toff(j, c, N / 2)], v[2 * c], v[2 * c + 1]);
+        for (int c = 0; c < N / 2; c++) unpack(at(b, j, c, N / 2), v[2 * c], v[2 * c + 1]);
     }
     __device__ __forceinline__ static void store(uint2* __restrict__ b, int j, const cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N / 2; c++) b[toff(j, c, N / 2)] = pack(v[2 * c], v[2 * c + 1]);
+        for (int c = 0; c < N / 2; c++) at(b, j, c, N / 2) = pack(v[2 * c], v[2 * c + 1]);
     }
     __device__ __forceinline__ static void load_stream(const uint2* __restrict__ b, int j, cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N / 2; c++) unpack(ld_stream(&b[toff(j, c, N / 2)]), v[2 * c], v[2 * c + 1]);
+        for (int c = 0; c < N / 2; c++) unpack(ld_stream(&at(b, j, c, N / 2)), v[2 * c], v[2 * c + 1]);
     }
     __device__ __forceinline__ static void store_stream(uint2* __restrict__ b, int j, const cx<float> (&v)[N])
     {
 #pragma unroll
-        for (int c = 0; c < N / 2; c++) st_stream(&b[toff(j, c, N / 2)], pack(v[2 * c], v[2 * c + 1]));
+        for (int c = 0; c < N / 2; c++) st_stream(&at(b, j, c, N / 2), pack(v[2 * c], v[2 * c + 1]));
     }
 };
 

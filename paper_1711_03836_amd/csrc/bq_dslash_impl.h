@@ -220,11 +220,11 @@ __device__ __forceinline__ void load_clover_block(const typename P::unit* __rest
 {
     if constexpr (P::id == PREC_F16) {
 #pragma unroll
-        for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(ld_stream(&C[toff(j, blk * 9 + u, 18)]), c[2 * u], c[2 * u + 1]);
+        for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(ld_stream(&at(C, j, blk * 9 + u, 18)), c[2 * u], c[2 * u + 1]);
     } else {
 #pragma unroll
         for (int k = 0; k < 18; k++) {
-            auto t = ld_stream(&C[toff(j, blk * 18 + k, 36)]);
+            auto t = ld_stream(&at(C, j, blk * 18 + k, 36));
             c[k] = {t.x, t.y};
         }
     }
@@ -256,7 +256,7 @@ __device__ __forceinline__ void load_spinor_part(const SpinorPtr<P>& f, int col,
         float s = f.s[col * f.sstride + j];
 #pragma unroll
         for (int u = 0; u < 3; u++) {
-            CxIO<P16, 2>::unpack(b[toff(j, blk * 3 + u, 6)], v[2 * u], v[2 * u + 1]);
+            CxIO<P16, 2>::unpack(at(b, j, blk * 3 + u, 6), v[2 * u], v[2 * u + 1]);
             v[2 * u] = cscale(s, v[2 * u]);
             v[2 * u + 1] = cscale(s, v[2 * u + 1]);
         }
@@ -264,7 +264,7 @@ __device__ __forceinline__ void load_spinor_part(const SpinorPtr<P>& f, int col,
         const typename P::unit* b = f.d + col * f.cstride;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            auto t = b[toff(j, blk * 6 + k, 12)];
+            auto t = at(b, j, blk * 6 + k, 12);
             v[k] = {t.x, t.y};
         }
     }
@@ -337,7 +337,7 @@ __device__ __forceinline__ void hh_load_spinor(const Args<P, PR>& A, int c, int 
     constexpr int SU = 12 / P::cpu;
     const typename P::unit* __restrict__ b = A.in.d + c * A.in.cstride;
 #pragma unroll
-    for (int k = 0; k < SU; k++) d.sp[r].u[k] = b[toff(d.jn, k, SU)];
+    for (int k = 0; k < SU; k++) d.sp[r].u[k] = at(b, d.jn, k, SU);
     if constexpr (P::id == PREC_F16) d.sc[r] = A.in.s[c * A.in.sstride + d.jn];
 }
 
@@ -353,7 +353,7 @@ __device__ __forceinline__ void hh_load_link(const Args<P, PR>& A, const Site& s
     const typename P::unit* __restrict__ U = A.U[(BW ? 1 - A.parity : A.parity) * 4 + MU];
     const int jl = BW ? d.jn : s.j;
 #pragma unroll
-    for (int k = 0; k < LU; k++) d.link.u[k] = ld_stream(&U[toff(jl, k, LU)]);
+    for (int k = 0; k < LU; k++) d.link.u[k] = ld_stream(&at(U, jl, k, LU));
 }
 
 template <class P, class PR, int R, int RECON, int H>
@@ -544,7 +544,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
                     const cx<T> w = caxpy(f, acc[r][blk * 6 + k], y[k]);
                     rv[k].re = fmadd(-al, (TR)w.re, rv[k].re);
                     rv[k].im = fmadd(-al, (TR)w.im, rv[k].im);
-                    st_stream(&rb[toff(j, blk * 6 + k, 12)], {rv[k].re, rv[k].im});
+                    st_stream(&at(rb, j, blk * 6 + k, 12), {rv[k].re, rv[k].im});
                     n += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
                 }
                 nrm[r] += n;
@@ -642,7 +642,7 @@ __device__ __forceinline__ void t_link(const Args<P, PR>& A, int par, int jl, PL
     Raw<P, link_cx<RECON>()> raw;
     const typename P::unit* __restrict__ U = A.U[par * 4 + 3];
 #pragma unroll
-    for (int k = 0; k < LU; k++) raw.u[k] = ld_stream(&U[toff(jl, k, LU)]);
+    for (int k = 0; k < LU; k++) raw.u[k] = ld_stream(&at(U, jl, k, LU));
     prep_link<P, RECON, true>(raw, L);
 }
 
