@@ -47,7 +47,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
-    ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=4)
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--other-inner", type=int, default=1, help="also time the other inner precision (1/0)")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests of the short serving run (0: skip)")

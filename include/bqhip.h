@@ -104,7 +104,9 @@ typedef struct {
     int inner_prec;    /* BQ_F64, BQ_F32 or BQ_F16 arithmetic/storage of the inner iterations */
     double delta;      /* reliable update when |r_inner| < delta * max|r| since the last update (0: 0.1) */
     int system;        /* BQ_SYS_* */
-    int chunk;         /* iterations between host convergence checks (0: default 16) */
+    int chunk;         /* iterations between reliable-update passes and host convergence checks
+                          (0: default 4).  A column that requests a reliable update idles until
+                          the end of its chunk; short chunks waste less, long ones launch less. */
     int use_graph;     /* 1: capture a chunk of iterations in a hipGraph and replay it */
 } bq_solve_params;
 

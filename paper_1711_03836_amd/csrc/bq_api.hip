@@ -754,7 +754,7 @@ static int cg_solve(bq_op op, Workspace* w, const bq_solve_params& prm, hipStrea
                                        : (double)n * ncol * (sX + (s64 + sX) + (sX + sP));
         acct.launches += prec == PREC_F64 ? 6 : 8;
     }
-    const int k = prm.chunk > 0 ? prm.chunk : 16;
+    const int k = prm.chunk > 0 ? prm.chunk : 4;
     const bool graph = prm.use_graph != 0;
     if (graph && (w->graph == nullptr || w->graph_chunk != k || w->graph_delta2 != w->cs.delta2)) {
         if (w->graph) {

@@ -138,14 +138,14 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("solve16")
     a.add_argument("--reps", type=int, default=2)
-    a.add_argument("--chunk", type=int, default=16)
+    a.add_argument("--chunk", type=int, default=4)
     b = sub.add_parser("trace48")
     b.add_argument("--dims", default="48,48,48,96")
     b.add_argument("--inner", choices=["f32", "f16"], default="f32")
     b.add_argument("--nnoise", type=int, default=64)
     b.add_argument("--block", type=int, default=16)
     b.add_argument("--seed", type=int, default=20171110, help="noise seed of the first block (block k: seed + k)")
-    b.add_argument("--chunk", type=int, default=16)
+    b.add_argument("--chunk", type=int, default=4)
     args = ap.parse_args()
     {"solve16": solve16, "trace48": trace48}[args.cmd](args)
 
