@@ -226,8 +226,10 @@ int bq_autotune(bq_op op, int prec, int nrhs);
  * alone and batched with others.  Single host thread per server.
  * ------------------------------------------------------------------------- */
 int bq_server_create(bq_context ctx, int slots, int chunk, bq_server* out);
-/* b: nrhs canonical host spinors; x: host array of the same size that receives the
- * solutions.  Both are owned by the caller and must stay valid until the request retires. */
+/* b: nrhs canonical spinors; x: an array of the same size that receives the solutions.
+ * Each may be host or device memory (the runtime tells them apart by address; device
+ * sources skip the PCIe transfers).  Both are owned by the caller and must stay valid
+ * until the request retires. */
 int bq_server_submit(bq_server s, bq_gauge g, double kappa, double csw, double mu, const double* b, double* x,
                      int nrhs, double tol, int inner_prec, int maxiter, uint64_t* ticket);
 /* One scheduling step; up to max_done tickets completed in this step are written to

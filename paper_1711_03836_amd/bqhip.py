@@ -317,12 +317,22 @@ class Server:
         self._keep = {}  # ticket -> (gauge, b, x): kept alive until retirement
 
     def submit(self, gauge: Gauge, b, kappa, csw, mu=0.0, tol=1e-10, inner_prec=BQ_F32, maxiter=100000):
-        b = np.ascontiguousarray(b, dtype=np.complex128)
-        x = np.zeros_like(b)
+        """b: (nrhs, V, 4, 3) complex128, numpy (host) or a contiguous torch tensor (host or device);
+        the solution x is returned by result() in the same kind of array."""
+        if torch is not None and isinstance(b, torch.Tensor):
+            if b.dtype != torch.complex128 or not b.is_contiguous():
+                raise ValueError("torch sources must be contiguous complex128")
+            x = torch.zeros_like(b)
+            if b.is_cuda:  # the server reads b on its own stream: finish the work that produced it
+                torch.cuda.current_stream(b.device).synchronize()
+            bp, xp = C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())
+        else:
+            b = np.ascontiguousarray(b, dtype=np.complex128)
+            x = np.zeros_like(b)
+            bp, xp = b.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p)
         t = C.c_uint64()
-        check(bq_server_submit(self.h, gauge.h, float(kappa), float(csw), float(mu), b.ctypes.data_as(C.c_void_p),
-                               x.ctypes.data_as(C.c_void_p), b.shape[0], float(tol), int(inner_prec), int(maxiter),
-                               C.byref(t)))
+        check(bq_server_submit(self.h, gauge.h, float(kappa), float(csw), float(mu), bp, xp, b.shape[0], float(tol),
+                               int(inner_prec), int(maxiter), C.byref(t)))
         self._keep[t.value] = (gauge, b, x)
         return t.value
 

@@ -1739,7 +1739,7 @@ static int admit(bq_server S, Request* q, Session* s)
     const size_t V = 2 * (size_t)g.Vh;
     const size_t bytes = (size_t)q->nrhs * V * 12 * 16;
     if (s->stage.bytes < bytes) CHK(s->stage.alloc(ctx, bytes));
-    HIPCHK(hipMemcpyAsync(s->stage.p, q->b, bytes, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->stage.p, q->b, bytes, hipMemcpyDefault, s->st));  // b in host or device memory
     q->slots.clear();
     for (int c = 0, k = 0; c < s->cap && k < q->nrhs; c++)
         if (!s->slot[c]) {
@@ -1836,7 +1836,7 @@ static int retire(bq_server S, Session* s, std::vector<Request*>& done)
             for (int p = 0; p < 2; p++)
                 HIPCHK(launch_spinor_export(col_arg(s->xfull, p, q->slots[k]), 1, g, p, PREC_F64,
                                             s->stage.as<double2>() + k * V * 12, st));
-        HIPCHK(hipMemcpyAsync(q->x_host, s->stage.p, bytes, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(q->x_host, s->stage.p, bytes, hipMemcpyDefault, st));  // x in host or device memory
         HIPCHK(hipStreamSynchronize(st));
     }
     HIPCHK(hipStreamSynchronize(st));

@@ -7,15 +7,15 @@ the device.  Each request draws its lattice uniformly from those four, kappa uni
 in [0.118, 0.124] (c_SW = 1.5, mu = 0), 1-12 right-hand sides and a relative residual
 of 1e-10, and is served by the continuous-batching server of the C library.
 
-Sources: a pool of seeded complex Gaussian fields per lattice is generated once; the
-sources of a request are pool fields shifted cyclically along x by request-dependent
-offsets, so every request has its own Gaussian sources without generating gigabytes
-of random numbers per request.
+Sources: a pool of seeded complex Gaussian fields per lattice is generated once and kept
+on the device; the sources of a request are pool fields shifted cyclically along x by
+request-dependent offsets (on the device), so every request has its own Gaussian sources
+and neither sources nor solutions cross PCIe.
 
 Latency = completion - arrival (queueing included), on the host clock.  --load L runs
-Poisson arrivals at L x the saturated throughput measured first with every request
-submitted at time zero (--saturation-requests of them); --qps sets the rate directly.
-Prints one JSON line.
+Poisson arrivals at L x the saturated throughput, measured first as a closed loop that
+keeps --saturation-outstanding requests submitted at all times (--saturation-requests of
+them); --qps sets the rate directly.  Prints one JSON line.
 """
 import argparse
 import json
@@ -41,6 +41,7 @@ class World:
     """Resident gauge fields and source pools for the serving lattices."""
 
     def __init__(self, bq, ctx, sizes=SIZES, eps=0.2, seed=4, pool=POOL):
+        import torch
         from paper_1711_03836_amd import inputs
         self.bq, self.ctx, self.sizes = bq, ctx, [tuple(s) for s in sizes]
         self.gauges, self.pools = {}, {}
@@ -48,18 +49,18 @@ class World:
             U = inputs.gauge_field(d, eps, seed=seed + k)
             self.gauges[d] = bq.Gauge(ctx, d, U, t_bc=-1)
             del U
-            self.pools[d] = inputs.gaussian_spinor(d, pool, seed=100 + k)
+            self.pools[d] = torch.from_numpy(inputs.gaussian_spinor(d, pool, seed=100 + k)).to("cuda")
 
     def sources(self, dims, nrhs, rseed):
-        """nrhs sources for one request: pool fields rolled along x by request-dependent amounts."""
+        """nrhs sources for one request (a device tensor): pool fields rolled along x by
+        request-dependent amounts."""
+        import torch
         pool = self.pools[dims]
         V = int(np.prod(dims))
-        b = np.empty((nrhs, V, 4, 3), dtype=np.complex128)
         shp = (dims[3], dims[2], dims[1], dims[0], 4, 3)
-        for k in range(nrhs):
-            src = pool[(rseed + k) % len(pool)].reshape(shp)
-            b[k] = np.roll(src, 2 * ((rseed * 7 + k) % (dims[0] // 2)), axis=3).reshape(V, 4, 3)
-        return b
+        cols = [torch.roll(pool[(rseed + k) % pool.shape[0]].reshape(shp), 2 * ((rseed * 7 + k) % (dims[0] // 2)),
+                           dims=3).reshape(V, 4, 3) for k in range(nrhs)]
+        return torch.stack(cols).contiguous()
 
 
 def make_requests(n, seed, sizes=SIZES, kappa=(0.118, 0.124), nrhs=(1, 12)):
@@ -72,8 +73,9 @@ def make_requests(n, seed, sizes=SIZES, kappa=(0.118, 0.124), nrhs=(1, 12)):
     return out
 
 
-def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_prec=1, progress=50):
-    """Serve `reqs`; arrivals at time 0 (qps None) or Poisson with rate qps.  Returns a summary dict."""
+def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_prec=1, progress=50, outstanding=8):
+    """Serve `reqs`: Poisson arrivals with rate qps, or (qps None) a closed loop that keeps
+    `outstanding` requests submitted.  Returns a summary dict."""
     rng = np.random.default_rng(seed)
     if qps:
         arrivals = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
@@ -85,11 +87,11 @@ def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_pre
     done_count = 0
     while done_count < len(reqs):
         now = time.perf_counter() - t0
-        while nxt < len(reqs) and arrivals[nxt] <= now:
+        while nxt < len(reqs) and arrivals[nxt] <= now and (qps or len(pending) < outstanding):
             r = reqs[nxt]
             b = world.sources(r["dims"], r["nrhs"], r["rseed"])
             tk = server.submit(world.gauges[r["dims"]], b, r["kappa"], csw, 0.0, tol, inner_prec)
-            pending[tk] = (nxt, t0 + arrivals[nxt])
+            pending[tk] = (nxt, t0 + arrivals[nxt] if qps else time.perf_counter())
             nxt += 1
         if not pending:
             time.sleep(max(0.0, min(0.01, arrivals[nxt] - now)))
@@ -98,7 +100,7 @@ def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_pre
         tdone = time.perf_counter()
         for tk in done:
             i, tarr = pending.pop(tk)
-            rc, info, x = server.result(tk)
+            rc, info, _ = server.result(tk)
             if rc != bq.BQ_OK:
                 raise RuntimeError(f"request {i} failed: {rc} {info}")
             lat.append(tdone - tarr)
@@ -118,6 +120,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--saturation-requests", type=int, default=200)
+    ap.add_argument("--saturation-outstanding", type=int, default=8)
     ap.add_argument("--load", type=float, nargs="*", default=[0.5, 0.8])
     ap.add_argument("--qps", type=float, default=None)
     ap.add_argument("--slots", type=int, default=16)
@@ -137,7 +140,8 @@ def main():
     sat = None
     if args.qps is None:
         server = bq.Server(ctx, args.slots, args.chunk)
-        r = run(bq, world, server, make_requests(args.saturation_requests, args.seed + 1), None, inner_prec=prec)
+        r = run(bq, world, server, make_requests(args.saturation_requests, args.seed + 1), None, inner_prec=prec,
+                outstanding=args.saturation_outstanding)
         server.close()
         sat = r["solves_per_s"]
         out["saturation"] = r

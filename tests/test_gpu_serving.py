@@ -73,3 +73,20 @@ def test_server_admission_by_budget(world):
     reqs = [(DIMS_A, G[DIMS_A][0], inputs.gaussian_spinor(DIMS_A, 3, seed=300 + i), 0.12, 1) for i in range(4)]
     out = serve(bq, ctx, reqs, slots=4)  # only one 3-column request fits at a time
     assert len(out) == 4 and all(v[0] == bq.BQ_OK for v in out.values())
+
+
+def test_server_device_buffers(world):
+    """Sources and solutions in device memory (torch tensors) give bitwise the host-memory results."""
+    import torch
+    bq, ctx, G = world
+    reqs = [(DIMS_A, G[DIMS_A][0], inputs.gaussian_spinor(DIMS_A, 2, seed=400 + i), 0.121 + 0.001 * i, 1)
+            for i in range(3)]
+    host = serve(bq, ctx, reqs)
+    dev_reqs = [(d, g, torch.from_numpy(b).to("cuda"), k, p) for (d, g, b, k, p) in reqs]
+    dev = serve(bq, ctx, dev_reqs)
+    for i in range(3):
+        rc_h, info_h, x_h = host[i]
+        rc_d, info_d, x_d = dev[i]
+        assert rc_h == rc_d == bq.BQ_OK
+        assert isinstance(x_d, torch.Tensor) and x_d.is_cuda
+        assert np.array_equal(x_h, x_d.cpu().numpy())
