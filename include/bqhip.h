@@ -60,7 +60,7 @@ extern "C" {
 #define BQ_ERR_CLOVER_NOT_HPD (-5)  /* a clover block is not positive definite (kappa c_SW too large) */
 #define BQ_ERR_BUSY (-6)            /* freeing a gauge field that live operators still use */
 #define BQ_ERR_DEVICE (-7)          /* a HIP runtime call failed */
-#define BQ_ERR_UNSUPPORTED (-8)     /* valid request this build does not provide */
+#define BQ_ERR_UNSUPPORTED (-8)     /* valid request this library version does not provide */
 
 enum { BQ_F64 = 0, BQ_F32 = 1, BQ_F16 = 2 };            /* storage precision of a field / inner solve */
 enum { BQ_EVEN = 0, BQ_ODD = 1, BQ_FULL = 2 };          /* sites a field holds */
