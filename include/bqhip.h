@@ -102,7 +102,8 @@ typedef struct {
     double tol;        /* stop when the FP64 true residual |b' - A x| <= tol |b'| (A, b' of the CG system) */
     int maxiter;       /* bound on inner CG iterations per right-hand side */
     int inner_prec;    /* BQ_F64, BQ_F32 or BQ_F16 arithmetic/storage of the inner iterations */
-    double delta;      /* reliable update when |r_inner| < delta * max|r| since the last update (0: 0.1) */
+    double delta;      /* reliable update when |r_inner| < delta * max|r| since the last update
+                          (0: 0.01 for FP32 inner iterations, 0.1 for FP16) */
     int system;        /* BQ_SYS_* */
     int chunk;         /* iterations between reliable-update passes and host convergence checks
                           (0: default 4).  A column that requests a reliable update idles until

@@ -227,7 +227,7 @@ class Op:
         check(bq_time_apply(self.h, kind, fin.h, fout.h, int(reps), _stream(stream), C.byref(ms), C.byref(by)))
         return ms.value, by.value
 
-    def solve(self, b, x, tol, system=BQ_SYS_NORMAL, inner_prec=BQ_F64, maxiter=100000, delta=0.1, chunk=4,
+    def solve(self, b, x, tol, system=BQ_SYS_NORMAL, inner_prec=BQ_F64, maxiter=100000, delta=0.0, chunk=4,
               use_graph=False, stream=None, raise_on_error=True):
         prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), float(delta), int(system), int(chunk),
                               int(bool(use_graph)))
@@ -238,7 +238,7 @@ class Op:
         return rc, [i.as_dict() for i in info]
 
     def trace(self, seed, nnoise, block, tol, inner_prec=BQ_F32, maxiter=100000, chunk=4, use_graph=False):
-        prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), 0.1, BQ_SYS_M, int(chunk),
+        prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), 0.0, BQ_SYS_M, int(chunk),
                               int(bool(use_graph)))
         t1 = (C.c_double * (2 * nnoise))()
         t2 = (C.c_double * (2 * nnoise))()

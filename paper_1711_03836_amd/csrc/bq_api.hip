@@ -734,7 +734,9 @@ static int cg_solve(bq_op op, Workspace* w, const bq_solve_params& prm, hipStrea
     // |b'|^2 -> rho, initial state
     HIPCHK(launch_norm2(PREC_F64, w->bp.all(), n, ncol, w->partial, w->pstride, st));
     HIPCHK(launch_fin_sum(w->partial, w->pstride, ncol, w->cs.rho, st));
-    const double delta = prm.delta > 0 ? prm.delta : 0.1;
+    // default threshold per inner precision: an FP32 inner solve reduces its residual 100x per
+    // cycle without loss (fewer FP64 reliable passes); FP16 storage limits it to about 10x
+    const double delta = prm.delta > 0 ? prm.delta : (prec == PREC_F32 ? 0.01 : 0.1);
     w->cs.delta2 = prec == PREC_F64 ? 0.0 : delta * delta;
     HIPCHK(launch_cg_init(w->cs, ncol, prm.tol * prm.tol, st));
     HIPCHK(launch_zero(PREC_F64, w->x.all(), n, ncol, nullptr, 0, st));
@@ -1957,7 +1959,7 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
     for (auto& s : S->sessions)
         if (s->used > 0) {
             Workspace* w = &s->w;
-            w->cs.delta2 = s->prec == PREC_F64 ? 0.0 : 0.01;
+            w->cs.delta2 = s->prec == PREC_F64 ? 0.0 : 0.01;  // reliable-update threshold delta = 0.1
             CHK(chunk(&s->stub, w, s->prec, S->chunk, s->st));
             HIPCHK(hipMemcpyAsync(w->h_status, w->cs.status, sizeof(int) * 4 * s->cap, hipMemcpyDeviceToHost, s->st));
             run.push_back(s.get());
