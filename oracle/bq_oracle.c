@@ -24,6 +24,12 @@
  *     (Eq. 1); periodic space, time boundary sign t_bc (-1 = antiperiodic);
  *   - even sites have (x1+x2+x3+x4) even; the Schur system lives on odd sites:
  *     Mhat = T_oo - kappa^2 D_oe T_ee^{-1} D_eo.
+ * Parity unpinned relative to the paper: the paper prints no operator value or
+ * worked example, so the basis, the trace subtraction, the sign of the clover
+ * term, the even-odd form, the noise convention and the link generator are
+ * pinned only as the definitions stated above.  Every function below is pinned
+ * by the CPU tests against closed forms, invariants, brute force or dense
+ * linear algebra.
  */
 #include <complex.h>
 #include <math.h>
