@@ -44,6 +44,33 @@ __host__ __device__ __forceinline__ size_t toff(int j, int c, int nunits)
         return tile + (size_t)(c & ~1) * kTile + 2 * lane + (c & 1);
     }
 }
+// Buffer-resource loads: the base address lives in scalar registers and each lane supplies a
+// 32-bit byte offset, so a load needs one vector register for its address instead of two and
+// no 64-bit address arithmetic.  Offsets from the resource base must stay below 4 GiB: with
+// V/2 < 2^24 sites per parity a spinor column (at most 192 B per site) and a link array (144 B)
+// do; clover arrays (576 B per site in FP64) are addressed from the base of the wave's tile.
+typedef unsigned bq_u4v __attribute__((ext_vector_type(4)));
+typedef unsigned bq_u2v_b __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffff, 0x00020000);
+}
+constexpr int kBufNT = 2;  // non-temporal cache policy
+template <int AUX>
+__device__ __forceinline__ bq_u4v buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ bq_u2v_b buf_load8(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+}
+__device__ __forceinline__ float buf_load4f(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 template <class U>
 __host__ __device__ __forceinline__ U& at(U* p, int j, int c, int nunits)
 {

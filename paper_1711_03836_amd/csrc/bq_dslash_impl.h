@@ -14,6 +14,10 @@
 
 #include "bq_kernels.h"
 
+#ifndef BQ_BUFFER_LOADS
+#define BQ_BUFFER_LOADS 1
+#endif
+
 namespace bq {
 namespace dslash {
 
@@ -122,6 +126,30 @@ __device__ __forceinline__ void unpack_raw(const Raw<P, N>& r, cx<typename P::re
 
 template <int RECON> constexpr int link_cx() { return RECON == 18 ? 9 : 6; }
 
+// The N storage units of site j (object of N units) through a buffer resource: one 16-byte
+// load per unit pair (8-byte units) or per unit (16-byte units), a last odd unit alone.
+template <class P, int N, int AUX>
+__device__ __forceinline__ void load_units(__amdgpu_buffer_rsrc_t rs, int j, Raw<P, N>& out)
+{
+    using U = typename P::unit;
+    constexpr int NU = N / P::cpu;
+    if constexpr (sizeof(U) == 16) {
+#pragma unroll
+        for (int c = 0; c < NU; c++) {
+            const bq_u4v v = buf_load16<AUX>(rs, (uint32_t)toff<U>(j, c, NU) * 16u);
+            out.u[c] = __builtin_bit_cast(U, v);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c + 1 < NU; c += 2) {
+            const bq_u4v v = buf_load16<AUX>(rs, (uint32_t)toff<U>(j, c, NU) * 8u);
+            out.u[c] = __builtin_bit_cast(U, bq_u2v_b{v.x, v.y});
+            out.u[c + 1] = __builtin_bit_cast(U, bq_u2v_b{v.z, v.w});
+        }
+        if constexpr (NU & 1) out.u[NU - 1] = __builtin_bit_cast(U, buf_load8<AUX>(rs, (uint32_t)toff<U>(j, NU - 1, NU) * 8u));
+    }
+}
+
 // link from its stored rows; with 12-real storage the third row of the SU(3) matrix is
 // conj(row0 x row1)
 template <class P, int RECON>
@@ -218,6 +246,54 @@ template <class P>
 __device__ __forceinline__ void load_clover_block(const typename P::unit* __restrict__ C, int j, int blk,
                                                   cx<typename P::real> (&c)[18])
 {
+#if BQ_BUFFER_LOADS
+    using U = typename P::unit;
+    constexpr int NU = 36 / P::cpu;  // units of both blocks
+    // The resource starts at the wave's own tile (j's tile is uniform over the wave), so offsets
+    // stay within one tile: an FP64 clover array of a large lattice exceeds 4 GiB.
+    const int tile = __builtin_amdgcn_readfirstlane(j >> kTileLog);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(C + (size_t)tile * NU * kTile);
+    j &= kTile - 1;
+    auto single = [&](int g) {
+        if constexpr (sizeof(U) == 16) return __builtin_bit_cast(U, buf_load16<kBufNT>(rs, (uint32_t)toff<U>(j, g, NU) * 16u));
+        else return __builtin_bit_cast(U, buf_load8<kBufNT>(rs, (uint32_t)toff<U>(j, g, NU) * 8u));
+    };
+    auto pair = [&](int g, U& a, U& b) {  // g even: units g, g+1 with one 16-byte load
+        if constexpr (sizeof(U) == 8) {
+            const bq_u4v v = buf_load16<kBufNT>(rs, (uint32_t)toff<U>(j, g, NU) * 8u);
+            a = __builtin_bit_cast(U, bq_u2v_b{v.x, v.y});
+            b = __builtin_bit_cast(U, bq_u2v_b{v.z, v.w});
+        }
+    };
+    if constexpr (P::id == PREC_F64) {
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+            const U t = single(blk * 18 + k);
+            c[k] = {t.x, t.y};
+        }
+    } else if constexpr (P::id == PREC_F32) {
+#pragma unroll
+        for (int m = 0; m < 9; m++) {
+            U a, b;
+            pair(blk * 18 + 2 * m, a, b);
+            c[2 * m] = {a.x, a.y};
+            c[2 * m + 1] = {b.x, b.y};
+        }
+    } else {  // 9 units per block: block 0 is units 0..8, block 1 units 9..17
+        U u[9];
+        if (blk == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; m++) pair(2 * m, u[2 * m], u[2 * m + 1]);
+            u[8] = single(8);
+        } else {
+            u[0] = single(9);
+#pragma unroll
+            for (int m = 0; m < 4; m++) pair(10 + 2 * m, u[1 + 2 * m], u[2 + 2 * m]);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; k++) CxIO<P16, 2>::unpack(u[k], c[2 * k], c[2 * k + 1]);
+    }
+#else
     if constexpr (P::id == PREC_F16) {
 #pragma unroll
         for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(ld_stream(&at(C, j, blk * 9 + u, 18)), c[2 * u], c[2 * u + 1]);
@@ -228,6 +304,7 @@ __device__ __forceinline__ void load_clover_block(const typename P::unit* __rest
             c[k] = {t.x, t.y};
         }
     }
+#endif
 }
 
 template <typename T>
@@ -334,11 +411,16 @@ struct HalfHop {
 template <class P, class PR, int R, int RECON>
 __device__ __forceinline__ void hh_load_spinor(const Args<P, PR>& A, int c, int r, HalfHop<P, R, RECON>& d)
 {
+#if BQ_BUFFER_LOADS
+    load_units<P, 12, 0>(buf_rsrc(A.in.d + c * A.in.cstride), d.jn, d.sp[r]);
+    if constexpr (P::id == PREC_F16) d.sc[r] = buf_load4f(buf_rsrc(A.in.s + c * A.in.sstride), (uint32_t)d.jn * 4u);
+#else
     constexpr int SU = 12 / P::cpu;
     const typename P::unit* __restrict__ b = A.in.d + c * A.in.cstride;
 #pragma unroll
     for (int k = 0; k < SU; k++) d.sp[r].u[k] = at(b, d.jn, k, SU);
     if constexpr (P::id == PREC_F16) d.sc[r] = A.in.s[c * A.in.sstride + d.jn];
+#endif
 }
 
 // neighbour index and link of half hop H: forward U_mu(x) stored at x, backward U_mu(x - mu)
@@ -352,8 +434,12 @@ __device__ __forceinline__ void hh_load_link(const Args<P, PR>& A, const Site& s
     d.jn = nbr(A.g, s, MU, BW ? -1 : +1);
     const typename P::unit* __restrict__ U = A.U[(BW ? 1 - A.parity : A.parity) * 4 + MU];
     const int jl = BW ? d.jn : s.j;
+#if BQ_BUFFER_LOADS
+    load_units<P, link_cx<RECON>(), kBufNT>(buf_rsrc(U), jl, d.link);
+#else
 #pragma unroll
     for (int k = 0; k < LU; k++) d.link.u[k] = ld_stream(&at(U, jl, k, LU));
+#endif
 }
 
 template <class P, class PR, int R, int RECON, int H>
@@ -580,7 +666,7 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
     const int lt = tblk * A.tpb + w / A.gw;
     const int grp = chunk * A.gw + gl;
     const int j = lt < A.g.ntiles ? tile_at(A.g, lt) * kTile + lane : A.g.ntiles * kTile;
-    const int c0 = grp * R;
+    const int c0 = __builtin_amdgcn_readfirstlane(grp * R);  // uniform over the wave
     bool act[R];
     bool any = false;
 #pragma unroll
@@ -658,7 +744,7 @@ __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos
     const int sg = rest / npos;
     const int w = threadIdx.x >> kTileLog;
     const int lane = threadIdx.x & (kTile - 1);
-    const int c0 = (ch * A.gw + w) * R;
+    const int c0 = __builtin_amdgcn_readfirstlane((ch * A.gw + w) * R);  // uniform over the wave
     const int Lt = A.g.L[3];
     bool act[R];
     bool any = false;

@@ -6,7 +6,8 @@ outputs one by one from their definition (Mhat and Mhat^dag at odd sites, M at a
     sampled reference element (the FP32 field-agreement bar);
   - the 12 point-source solve (FP32 inner, FP64 reliable updates, tol 1e-10): at every sampled site
     the residual b - M x, computed by the oracle from the GPU solution, is bounded by the global
-    residual norm the library reports, and that norm is small.
+    residual norm the library reports, and that norm is small;
+  - FP64 Mhat on 48^3x160, where a parity's FP64 clover array is larger than 4 GiB.
 """
 import numpy as np
 import pytest
@@ -119,3 +120,39 @@ def test_single_source_16x32_oracle_residual(inner):
           f"reported {info[0]['full_rel_resid']:.3e}", flush=True)
     assert abs(rel - info[0]["full_rel_resid"]) <= 0.01 * rel + 1e-15
     assert rel < 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_large_lattice_fp64_mhat_sampled():
+    """48^3x160 (V/2 = 8.8M sites per parity), where one FP64 clover array of a parity takes
+    4.9 GB, more than a 32-bit byte offset reaches: FP64 Mhat on one Gaussian column against the
+    oracle at sampled odd sites, most of them in the last 25 time slices, whose clover entries lie
+    beyond the first 4 GiB of the array (1e-12 relative to the largest sampled element).  The
+    links are a 48^3x32 field U = exp(0.2 i H) repeated five times along t."""
+    from paper_1711_03836_amd import bqhip as bq
+    dims = (48, 48, 48, 160)
+    base = inputs.gauge_field((48, 48, 48, 32), 0.2, seed=48160)
+    U = np.concatenate([base] * 5, axis=1)
+    del base
+    psi = inputs.gaussian_spinor(dims, 1, seed=7)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.124, 1.5, 0.1)
+    fi = bq.Field(ctx, dims, bq.BQ_ODD, bq.BQ_F64, 1)
+    fo = bq.Field(ctx, dims, bq.BQ_ODD, bq.BQ_F64, 1)
+    fi.put(psi)
+    op.apply(bq.BQ_OP_MHAT, fi, fo)
+    got = fo.get()[0]
+    rng = np.random.default_rng(160)
+    L = dims
+    pts = [(0, 0, 0, 159), (47, 47, 47, 158), (1, 0, 0, 135), (0, 47, 0, 136), (13, 5, 40, 0)]
+    while len(pts) < 160:
+        t = int(rng.integers(135, 160)) if len(pts) % 4 else int(rng.integers(160))
+        pts.append((int(rng.integers(48)), int(rng.integers(48)), int(rng.integers(48)), t))
+    sites = np.array(sorted({x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3]))
+                             for x in pts if sum(x) % 2 == 1}), dtype=np.int64)
+    assert len(sites) >= 40
+    want = orc.Mhat_sites(dims, U, 0.124, 1.5, psi[0], sites, t_bc=-1, mu=0.1)
+    err = np.abs(got[sites] - want).max() / np.abs(want).max()
+    print(f"[large] 48^3x160 FP64 Mhat at {len(sites)} odd sites: max rel err {err:.2e}", flush=True)
+    assert err < 1e-12, err
