@@ -14,6 +14,7 @@ this module raises ImportError.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -171,6 +172,24 @@ class Context:
 
     def tune_set(self, prec, nrhs, recon, R, bs, march=0):
         check(bq_tune_set(self.h, prec, nrhs, recon, R, bs, march))
+
+    def save_tuning(self, path, keys, lattice=None):
+        """Write the stencil configurations of the (prec, nrhs) pairs in `keys` to a JSON file,
+        with the lattice they were tuned on (informational), for load_tuning in a later process."""
+        entries = [{"prec": int(p), "nrhs": int(n), "config": list(self.tune_get(p, n))} for p, n in keys]
+        with open(path, "w") as f:
+            json.dump({"lattice": list(lattice) if lattice else None, "entries": entries}, f, indent=1)
+
+    def load_tuning(self, path):
+        """Apply the configurations a save_tuning file holds; returns the (prec, nrhs) pairs set."""
+        with open(path) as f:
+            doc = json.load(f)
+        keys = []
+        for e in doc["entries"]:
+            recon, R, bs, march = e["config"]
+            self.tune_set(e["prec"], e["nrhs"], recon, R, bs, march)
+            keys.append((e["prec"], e["nrhs"]))
+        return keys
 
     def close(self):
         if self.h:

@@ -413,3 +413,18 @@ def test_march_larger_lattice_bitwise(bq, prec, recon, R, bs, march):
         assert all(c["converged"] for c in info)
         xs[m] = x
     assert np.array_equal(xs[0], xs[march])
+
+
+def test_tuning_json_roundtrip(bq, setup, tmp_path):
+    """Autotuned and hand-set stencil configurations survive save_tuning / load_tuning into a
+    fresh context, and the operator's results do not depend on them."""
+    ctx, G, op, ref, U = setup
+    op.autotune(bq.BQ_F32, 4)
+    ctx.tune_set(bq.BQ_F64, 1, 18, 1, 256, 0)
+    path = tmp_path / "tune.json"
+    ctx.save_tuning(path, [(bq.BQ_F32, 4), (bq.BQ_F64, 1)], lattice=DIMS)
+    ctx2 = bq.Context(0)
+    assert ctx2.load_tuning(path) == [(bq.BQ_F32, 4), (bq.BQ_F64, 1)]
+    assert ctx2.tune_get(bq.BQ_F32, 4) == ctx.tune_get(bq.BQ_F32, 4)
+    assert ctx2.tune_get(bq.BQ_F64, 1) == (18, 1, 256, 0)
+    ctx2.close()
