@@ -242,7 +242,7 @@ __device__ __forceinline__ void hop_product(const PLink<P, RECON, BW>& L, const 
 // block 0 acts on spins 0,1 (components 0..5), block 1 on spins 2,3.
 // ---------------------------------------------------------------------------
 
-template <class P>
+template <class P, int LA>
 __device__ __forceinline__ void load_clover_block(const typename P::unit* __restrict__ C, int j, int blk,
                                                   cx<typename P::real> (&c)[18])
 {
@@ -255,12 +255,12 @@ __device__ __forceinline__ void load_clover_block(const typename P::unit* __rest
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(C + (size_t)tile * NU * kTile);
     j &= kTile - 1;
     auto single = [&](int g) {
-        if constexpr (sizeof(U) == 16) return __builtin_bit_cast(U, buf_load16<kBufNT>(rs, (uint32_t)toff<U>(j, g, NU) * 16u));
-        else return __builtin_bit_cast(U, buf_load8<kBufNT>(rs, (uint32_t)toff<U>(j, g, NU) * 8u));
+        if constexpr (sizeof(U) == 16) return __builtin_bit_cast(U, buf_load16<LA>(rs, (uint32_t)toff<U>(j, g, NU) * 16u));
+        else return __builtin_bit_cast(U, buf_load8<LA>(rs, (uint32_t)toff<U>(j, g, NU) * 8u));
     };
     auto pair = [&](int g, U& a, U& b) {  // g even: units g, g+1 with one 16-byte load
         if constexpr (sizeof(U) == 8) {
-            const bq_u4v v = buf_load16<kBufNT>(rs, (uint32_t)toff<U>(j, g, NU) * 8u);
+            const bq_u4v v = buf_load16<LA>(rs, (uint32_t)toff<U>(j, g, NU) * 8u);
             a = __builtin_bit_cast(U, bq_u2v_b{v.x, v.y});
             b = __builtin_bit_cast(U, bq_u2v_b{v.z, v.w});
         }
@@ -425,7 +425,7 @@ __device__ __forceinline__ void hh_load_spinor(const Args<P, PR>& A, int c, int 
 
 // neighbour index and link of half hop H: forward U_mu(x) stored at x, backward U_mu(x - mu)
 // stored at the neighbour (other parity)
-template <class P, class PR, int R, int RECON, int H>
+template <class P, class PR, int R, int RECON, int H, int LA>
 __device__ __forceinline__ void hh_load_link(const Args<P, PR>& A, const Site& s, HalfHop<P, R, RECON>& d)
 {
     constexpr int MU = H >> 1;
@@ -435,18 +435,18 @@ __device__ __forceinline__ void hh_load_link(const Args<P, PR>& A, const Site& s
     const typename P::unit* __restrict__ U = A.U[(BW ? 1 - A.parity : A.parity) * 4 + MU];
     const int jl = BW ? d.jn : s.j;
 #if BQ_BUFFER_LOADS
-    load_units<P, link_cx<RECON>(), kBufNT>(buf_rsrc(U), jl, d.link);
+    load_units<P, link_cx<RECON>(), LA>(buf_rsrc(U), jl, d.link);
 #else
 #pragma unroll
     for (int k = 0; k < LU; k++) d.link.u[k] = ld_stream(&at(U, jl, k, LU));
 #endif
 }
 
-template <class P, class PR, int R, int RECON, int H>
+template <class P, class PR, int R, int RECON, int H, int LA>
 __device__ __forceinline__ void hh_load(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
                                         HalfHop<P, R, RECON>& d)
 {
-    hh_load_link<P, PR, R, RECON, H>(A, s, d);
+    hh_load_link<P, PR, R, RECON, H, LA>(A, s, d);
 #pragma unroll
     for (int r = 0; r < R; r++)
         if (act[r]) hh_load_spinor(A, c0 + r, r, d);
@@ -497,45 +497,47 @@ constexpr bool prefetch_hops()
     return BQ_PREFETCH && (P::id == PREC_F64 ? R <= 1 : (P::id == PREC_F32 ? R <= 2 : R <= 3));
 }
 
-template <class P, class PR, int R, int DAG, int RECON, int H, bool PF = prefetch_hops<P, R>()>
+template <class P, class PR, int R, int DAG, int RECON, int H, bool PF, int LA>
 __device__ __forceinline__ void hh_step(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
                                         HalfHop<P, R, RECON> (&d)[2], cx<typename P::real> (&acc)[R][12])
 {
     if constexpr (PF) {
-        if constexpr (H < 7) hh_load<P, PR, R, RECON, H + 1>(A, s, act, c0, d[(H + 1) & 1]);
+        if constexpr (H < 7) hh_load<P, PR, R, RECON, H + 1, LA>(A, s, act, c0, d[(H + 1) & 1]);
         hh_compute<P, PR, R, DAG, RECON, H, false>(A, s, act, c0, d[H & 1], acc);
     } else {
-        hh_load_link<P, PR, R, RECON, H>(A, s, d[0]);
+        hh_load_link<P, PR, R, RECON, H, LA>(A, s, d[0]);
         hh_compute<P, PR, R, DAG, RECON, H, true>(A, s, act, c0, d[0], acc);
     }
     phase_end(act, acc);
 }
 
-template <class P, class PR, int R, int DAG, int RECON>
+template <class P, class PR, int R, int DAG, int RECON, int LA>
 __device__ __forceinline__ void hop_all(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
                                         cx<typename P::real> (&acc)[R][12])
 {
+    constexpr bool PF = prefetch_hops<P, R>();
     HalfHop<P, R, RECON> d[2];
-    if constexpr (prefetch_hops<P, R>()) hh_load<P, PR, R, RECON, 0>(A, s, act, c0, d[0]);
-    hh_step<P, PR, R, DAG, RECON, 0>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 1>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 2>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 3>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 4>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 5>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 6>(A, s, act, c0, d, acc);
-    hh_step<P, PR, R, DAG, RECON, 7>(A, s, act, c0, d, acc);
+    if constexpr (PF) hh_load<P, PR, R, RECON, 0, LA>(A, s, act, c0, d[0]);
+    hh_step<P, PR, R, DAG, RECON, 0, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 1, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 2, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 3, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 4, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 5, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 6, PF, LA>(A, s, act, c0, d, acc);
+    hh_step<P, PR, R, DAG, RECON, 7, PF, LA>(A, s, act, c0, d, acc);
 }
 
 // Epilogue of one tile for R columns: the linear combination and clover factor the caller
 // asked for (EPI), the store, and for EPI_TV / EPI_TVR the per-wave |.|^2 partials.  Lanes with
 // no active column pass nrm = 0 to the wave reduction.
-template <class P, class PR, int R, int EPI, bool PC>
+template <class P, class PR, int R, int EPI, bool PC, int LA>
 __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool (&act)[R], bool any, int c0,
                                          cx<typename P::real> (&acc)[R][12])
 {
     using T = typename P::real;
     using TR = typename PR::real;
+    constexpr int CA = PC ? kBufNT : LA;  // per-column clover is read by one wave only
     double nrm[R];
 #pragma unroll
     for (int r = 0; r < R; r++) nrm[r] = 0.0;
@@ -560,11 +562,11 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 #pragma unroll
             for (int blk = 0; blk < 2; blk++) {
                 cx<T> cb[18];
-                if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
+                if constexpr (!PC) load_clover_block<P, CA>(A.clov, j, blk, cb);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     if (!act[r]) continue;
-                    if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
+                    if constexpr (PC) load_clover_block<P, CA>(A.cclov[c0 + r], j, blk, cb);
                     cx<T> x[6];
 #pragma unroll
                     for (int k = 0; k < 6; k++) x[k] = acc[r][blk * 6 + k];
@@ -581,11 +583,11 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 #pragma unroll
         for (int blk = 0; blk < 2; blk++) {
             cx<T> cb[18];
-            if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
+            if constexpr (!PC) load_clover_block<P, CA>(A.clov, j, blk, cb);
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (!act[r]) continue;
-                if constexpr (PC) load_clover_block<P>(A.cclov[c0 + r], j, blk, cb);
+                if constexpr (PC) load_clover_block<P, CA>(A.cclov[c0 + r], j, blk, cb);
                 const T f = colf<PC>(A, c0 + r);
                 cx<T> x[6], y[6];
                 load_spinor_part(A.v, c0 + r, j, blk, x);
@@ -610,12 +612,12 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 #pragma unroll
         for (int blk = 0; blk < 2; blk++) {
             cx<T> cb[18];
-            if constexpr (!PC) load_clover_block<P>(A.clov, j, blk, cb);
+            if constexpr (!PC) load_clover_block<P, CA>(A.clov, j, blk, cb);
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (!act[r]) continue;
                 const int c = c0 + r;
-                if constexpr (PC) load_clover_block<P>(A.cclov[c], j, blk, cb);
+                if constexpr (PC) load_clover_block<P, CA>(A.cclov[c], j, blk, cb);
                 const T f = colf<PC>(A, c);
                 const TR al = A.alpha ? (TR)A.alpha[c] : TR(1);
                 cx<T> x[6], y[6];
@@ -656,7 +658,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 // One work item: tile block `tblk` (tpb tiles) x column-group chunk `chunk` (gw groups of R
 // columns).  Wave w of the workgroup handles tile w / gw and group w % gw, so all groups of a
 // tile run side by side and share the links and clover through L1/L2.
-template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA>
 __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chunk)
 {
     using T = typename P::real;
@@ -682,9 +684,9 @@ __device__ __forceinline__ void hop_item(const Args<P, PR>& A, int tblk, int chu
         for (int r = 0; r < R; r++)
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
-        hop_all<P, PR, R, DAG, RECON>(A, s, act, c0, acc);
+        hop_all<P, PR, R, DAG, RECON, LA>(A, s, act, c0, acc);
     }
-    epilogue<P, PR, R, EPI, PC>(A, j, act, any, c0, acc);
+    epilogue<P, PR, R, EPI, PC, LA>(A, j, act, any, c0, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -732,7 +734,7 @@ __device__ __forceinline__ void t_link(const Args<P, PR>& A, int par, int jl, PL
     prep_link<P, RECON, true>(raw, L);
 }
 
-template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA>
 __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos, int seg, int nseg)
 {
     using T = typename P::real;
@@ -767,7 +769,7 @@ __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos
         const int t = (t0 + q) % Lt;
         const Site s = site_at(t);
         HalfHop<P, R, RECON> d;
-        hh_load<P, PR, R, RECON, 7>(A, s, act, c0, d);
+        hh_load<P, PR, R, RECON, 7, LA>(A, s, act, c0, d);
         PLink<P, RECON, true> L;
         prep_link<P, RECON, true>(d.link, L);
         t_backward<P, PR, R, DAG, RECON>(d, L, t == 0 ? A.eb_bc : A.eb, act, q == 0 ? B0 : B1, q == 0 ? K0 : K1);
@@ -783,14 +785,14 @@ __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos
             for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
         // the carried terms take the registers of a second prefetch buffer: no prefetching here
         HalfHop<P, R, RECON> d[2];
-        hh_step<P, PR, R, DAG, RECON, 0, false>(A, s, act, c0, d, acc);
-        hh_step<P, PR, R, DAG, RECON, 1, false>(A, s, act, c0, d, acc);
-        hh_step<P, PR, R, DAG, RECON, 2, false>(A, s, act, c0, d, acc);
-        hh_step<P, PR, R, DAG, RECON, 3, false>(A, s, act, c0, d, acc);
-        hh_step<P, PR, R, DAG, RECON, 4, false>(A, s, act, c0, d, acc);
-        hh_step<P, PR, R, DAG, RECON, 5, false>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 0, false, LA>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 1, false, LA>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 2, false, LA>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 3, false, LA>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 4, false, LA>(A, s, act, c0, d, acc);
+        hh_step<P, PR, R, DAG, RECON, 5, false, LA>(A, s, act, c0, d, acc);
         // forward time hop; its spinors also give the backward time term of plane t + 2
-        hh_load<P, PR, R, RECON, 6>(A, s, act, c0, d[0]);
+        hh_load<P, PR, R, RECON, 6, LA>(A, s, act, c0, d[0]);
         hh_compute<P, PR, R, DAG, RECON, 6, false>(A, s, act, c0, d[0], acc);
         // backward time hop of plane t, kept from plane t - 2
 #pragma unroll
@@ -817,17 +819,17 @@ __global__ __launch_bounds__(512) void k_hop_march(const Args<P, PR> A, int npos
             K0[r] = K1[r];
             K1[r] = kk;
         }
-        epilogue<P, PR, R, EPI, PC>(A, s.j, act, true, c0, acc);
+        epilogue<P, PR, R, EPI, PC, LA>(A, s.j, act, true, c0, acc);
     }
 }
 
 // One work item per workgroup; blocks are mapped XCD-contiguously (see xcd_remap).
-template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC>
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA>
 __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
 {
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int tblk = lb / A.nch;
-    hop_item<P, PR, R, DAG, EPI, RECON, PC>(A, tblk, lb - tblk * A.nch);
+    hop_item<P, PR, R, DAG, EPI, RECON, PC, LA>(A, tblk, lb - tblk * A.nch);
 }
 
 template <class P>
@@ -870,6 +872,10 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
     }
     if (L.percol && L.ncol > kMaxCols) return hipErrorInvalidValue;
     const int G = (L.ncol + R - 1) / R;
+    // With more than one column group per tile, the other groups' waves read the same links
+    // (and, without per-column clover, the same clover) soon after: load those through the
+    // caches.  With one group they are read once and streamed (non-temporal).
+    const bool shared = G > 1;
     if (L.march > 0) {
         // t-marching: one tile position x column-group chunk x time segment per workgroup,
         // at most bs / 64 column groups per workgroup
@@ -881,8 +887,12 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
         const int npos = L.g.ntiles / L.g.L[3];
         const int nseg = L.g.L[3] / L.march;
         A.nblk = npos * nseg;
-        hipLaunchKernelGGL((k_hop_march<P, PR, R, DAG, EPI, RECON, PC>), dim3(A.nblk * A.nch), dim3(kTile * A.gw), 0,
-                           st, A, npos, L.march, nseg);
+        if (shared)
+            hipLaunchKernelGGL((k_hop_march<P, PR, R, DAG, EPI, RECON, PC, 0>), dim3(A.nblk * A.nch), dim3(kTile * A.gw),
+                               0, st, A, npos, L.march, nseg);
+        else
+            hipLaunchKernelGGL((k_hop_march<P, PR, R, DAG, EPI, RECON, PC, kBufNT>), dim3(A.nblk * A.nch),
+                               dim3(kTile * A.gw), 0, st, A, npos, L.march, nseg);
         return hipGetLastError();
     }
     // L.bs = sites per workgroup (a multiple of 64); at most 512 threads per workgroup
@@ -891,7 +901,11 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
     A.gw = std::max(1, std::min(G, 512 / (tpb * kTile)));
     A.nch = (G + A.gw - 1) / A.gw;
     A.nblk = (L.g.ntiles + tpb - 1) / tpb;
-    hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON, PC>), dim3(A.nblk * A.nch), dim3(tpb * kTile * A.gw), 0, st, A);
+    if (shared)
+        hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON, PC, 0>), dim3(A.nblk * A.nch), dim3(tpb * kTile * A.gw), 0, st, A);
+    else
+        hipLaunchKernelGGL((k_hop<P, PR, R, DAG, EPI, RECON, PC, kBufNT>), dim3(A.nblk * A.nch), dim3(tpb * kTile * A.gw), 0,
+                           st, A);
     return hipGetLastError();
 }
 
