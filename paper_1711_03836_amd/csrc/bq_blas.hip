@@ -279,9 +279,17 @@ __global__ void k_z2_noise(uint64_t seed, long n0, const Geom g, int parity, Spi
 
 __device__ double block_sum(const double* __restrict__ part, int n)
 {
+    // eight independent partial sums per thread keep eight loads in flight; which element goes
+    // to which sum depends on n only, so the result is deterministic for a given lattice
     __shared__ double w[4];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 7 * 256 < n; i += 8 * 256) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) a[k] += part[i + k * 256];
+    }
+    for (; i < n; i += 256) a[0] += part[i];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
     __syncthreads();
