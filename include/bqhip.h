@@ -39,7 +39,9 @@
  *     that stream; NULL selects the context's own stream.  bq_apply is
  *     asynchronous on that stream; every other call returns when its results
  *     are complete.
- *   - All lattice extents must be even and >= 2.
+ *   - All lattice extents must be even and >= 2, with fewer than 2^24 sites
+ *     per parity (V/2 < 16777216; 48^3x96 has 5.3 M, 64^3x120 has 15.7 M);
+ *     BQ_ERR_INVALID otherwise.
  *   - A context is not thread-safe: one host thread per context at a time.
  */
 #ifndef BQHIP_H
