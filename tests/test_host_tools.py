@@ -1,4 +1,4 @@
-"""Host-side tools: the benchmark's one-GPU guard and the rocprofv3 summary script (CPU only)."""
+"""Host-side tools: the benchmark's one-GPU guard, the rocprofv3 summary script and the tuning file (CPU only)."""
 import csv
 import json
 import os
@@ -47,3 +47,31 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     assert abs(d["fetch"]["factor"] - 2.0) < 1e-12 and abs(d["write"]["factor"] - 1.0) < 1e-12
     assert abs(d["traffic_bytes"] - (2000.0 + 300.0) * 1024) < 1e-6
     assert d["tune"] == [12, 3, 128, 0] and d["source_digest"] == ps.source_digest()
+
+
+def test_tuning_file_round_trip(tmp_path):
+    """Context.save_tuning / load_tuning write and apply the (prec, nrhs) -> (recon, R, bs, march)
+    table through tune_get / tune_set only; checked here on stand-in contexts (no device)."""
+    sys.path.insert(0, ROOT)
+    from paper_1711_03836_amd import bqhip as bq
+
+    class Src:
+        table = {(1, 12): (12, 3, 128, 0), (0, 1): (18, 1, 64, 16)}
+
+        def tune_get(self, prec, nrhs):
+            return self.table[(prec, nrhs)]
+
+    class Dst:
+        def __init__(self):
+            self.set = []
+
+        def tune_set(self, prec, nrhs, recon, R, bs, march=0):
+            self.set.append((prec, nrhs, recon, R, bs, march))
+
+    path = tmp_path / "tune.json"
+    bq.Context.save_tuning(Src(), path, [(1, 12), (0, 1)], lattice=(32, 32, 32, 64))
+    doc = json.loads(path.read_text())
+    assert doc["lattice"] == [32, 32, 32, 64]
+    dst = Dst()
+    assert bq.Context.load_tuning(dst, path) == [(1, 12), (0, 1)]
+    assert dst.set == [(1, 12, 12, 3, 128, 0), (0, 1, 18, 1, 64, 16)]
