@@ -501,6 +501,51 @@ int or_cg(const int L[4], const cplx *U, const cplx *T, const cplx *Tinv, double
 }
 
 /* ------------------------------------------------------------------ */
+/* Derivatives of M with respect to the action's parameters (the        */
+/* reweighting traces Tr(M^-1 dM/dp) named in the abstract)              */
+/* ------------------------------------------------------------------ */
+
+/* S(x) = sum_{mu<nu} sigma_{mu nu} (x) Fh_{mu nu}(x), dense 12x12 per site: the clover term of
+ * Eq. 2 without its factor kappa c_SW, so that T = 1 + kappa c_SW S, dT/dkappa = c_SW S and
+ * dT/dc_SW = kappa S. */
+void or_sigma_F(const int L[4], const cplx *U, cplx *S)
+{
+    init_algebra();
+    long V = vol(L);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < V; i++) {
+        cplx *Si = S + i * NSC * NSC;
+        for (int k = 0; k < NSC * NSC; k++) Si[k] = 0;
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++) {
+                cplx Fh[9];
+                or_field_strength_site(L, U, i, mu, nu, Fh);
+                for (int s = 0; s < 4; s++)
+                    for (int a = 0; a < 3; a++)
+                        for (int t = 0; t < 4; t++)
+                            for (int b = 0; b < 3; b++)
+                                Si[(s * 3 + a) * NSC + t * 3 + b] += SIG[mu][nu][s][t] * Fh[a * 3 + b];
+            }
+    }
+}
+
+/* (dD/dmu psi)(x): only the time hops of Eq. 1 depend on mu; the forward hop's factor e^{+mu}
+ * differentiates to +e^{+mu}, the backward hop's e^{-mu} to -e^{-mu}; the boundary sign stays. */
+void or_hop_dmu(const int L[4], const cplx *U, int t_bc, double mu_ch, const cplx *in, cplx *out)
+{
+    init_algebra();
+    long V = vol(L);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < V; i++) {
+        cplx *o = out + i * NSC;
+        for (int k = 0; k < NSC; k++) o[k] = 0;
+        long f = neighbour(L, i, 3, +1), b = neighbour(L, i, 3, -1);
+        add_hop_term(o, link(U, V, 3, i), 0, 3, -1.0, coef_fwd(L, i, 3, t_bc, mu_ch), in + f * NSC);
+        add_hop_term(o, link(U, V, 3, b), 1, 3, +1.0, -coef_bwd(L, i, 3, t_bc, mu_ch), in + b * NSC);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Gauge observables                                                    */
 /* ------------------------------------------------------------------ */
 

@@ -62,6 +62,8 @@ def _load():
         "or_M_sites": (None, [L4, _cp, d, d, i, d, i, _cp, l, _cp, _cp]),
         "or_clover_sites": (None, [L4, _cp, d, d, l, _cp, _cp]),
         "or_num_threads": (i, []),
+        "or_sigma_F": (None, [L4, _cp, _cp]),
+        "or_hop_dmu": (None, [L4, _cp, i, d, _cp, _cp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -203,6 +205,25 @@ def cg(dims, U, T, Tinv, kappa, b, system, tol, maxiter, t_bc=-1, mu=0.0):
     return x, it
 
 
+def sigma_F(dims, U):
+    """S(x) = sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x), the clover term of Eq. 2 without kappa c_SW,
+    shape (V, 12, 12): T = 1 + kappa c_SW S."""
+    lib = _load()
+    U = _c(U)
+    S = np.empty((volume(dims), 12, 12), dtype=np.complex128)
+    lib.or_sigma_F(_dims(dims), _p(U), _p(S))
+    return S
+
+
+def hop_dmu(dims, U, psi, t_bc=-1, mu=0.0):
+    """(dD/dmu) psi: the time hops of Eq. 1 with e^{+mu} -> +e^{+mu} (forward), e^{-mu} -> -e^{-mu} (backward)."""
+    lib = _load()
+    U = _c(U); psi = _c(psi)
+    out = np.empty_like(psi)
+    lib.or_hop_dmu(_dims(dims), _p(U), int(t_bc), float(mu), _p(psi), _p(out))
+    return out
+
+
 def plaquette(dims, U):
     return _load().or_plaquette(_dims(dims), _p(_c(U)))
 
@@ -290,6 +311,20 @@ class Operator:
 
     def cg(self, b, system, tol, maxiter=100000):
         return cg(self.dims, self.U, self.T, self.Tinv, self.kappa, b, system, tol, maxiter, self.t_bc, self.mu)
+
+    def dM(self, psi, param):
+        """(dM/dp) psi for p = 'kappa', 'csw' or 'mu', with M = T - kappa D, T = 1 + kappa c_SW S:
+        dM/dkappa = c_SW S - D, dM/dc_SW = kappa S, dM/dmu = -kappa dD/dmu."""
+        if param == "mu":
+            return -self.kappa * hop_dmu(self.dims, self.U, psi, self.t_bc, self.mu)
+        if not hasattr(self, "_S"):
+            self._S = sigma_F(self.dims, self.U)
+        Spsi = np.einsum("ikl,il->ik", self._S, psi.reshape(self.V, 12)).reshape(psi.shape)
+        if param == "kappa":
+            return self.csw * Spsi - self.hop(psi)
+        if param == "csw":
+            return self.kappa * Spsi
+        raise ValueError(param)
 
     def solve_M(self, b, tol, maxiter=100000):
         """x = M^-1 b through the odd-site Schur system: bhat, CG on Mhat^dag Mhat, reconstruction."""

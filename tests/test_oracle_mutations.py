@@ -2,8 +2,9 @@
 
 Each case copies oracle/bq_oracle.c to a temporary directory, applies one
 plausible mistake (a flipped sign, a dropped term, a wrong index, a missing
-adjoint), compiles it with gcc and runs tests/test_oracle_pins.py against that
-build.  The pins must fail for every mutation.
+adjoint, a dropped leaf, a transposed link, a wrong power of kappa), compiles it
+with gcc and runs the pins (tests/test_oracle_pins.py, tests/test_oracle_solver_pins.py)
+against that build.  The pins must fail for every mutation.
 """
 import os
 import subprocess
@@ -32,7 +33,18 @@ MUTATIONS = {
     "cg residual update": ("r[k] -= alpha * Ap[k];", "r[k] -= alpha * q[k];"),
     "noise imaginary bit": ("(z >> 62) & 1", "(z >> 61) & 1"),
     "hop accumulates by assignment": ("out[s * 3 + a] += coef * acc;", "out[s * 3 + a] = coef * acc;"),
+    "dropped clover leaf": ("m3_mul(P, link(U, V, nu, xmn), P);\n    for (int k = 0; k < 9; k++) Q[k] += P[k];",
+                            "m3_mul(P, link(U, V, nu, xmn), P);"),
+    "transposed forward link": ("cplx w = W_dag ? conj(W[b * 3 + a]) : W[a * 3 + b];",
+                                "cplx w = W_dag ? conj(W[b * 3 + a]) : W[b * 3 + a];"),
+    "wrong kappa power in the Schur form": ("out[i * NSC + k] -= kappa * kappa * a[i * NSC + k]",
+                                            "out[i * NSC + k] -= kappa * a[i * NSC + k]"),
+    "dD/dmu backward sign": ("-coef_bwd(L, i, 3, t_bc, mu_ch), in + b * NSC",
+                             "coef_bwd(L, i, 3, t_bc, mu_ch), in + b * NSC"),
+    "sigma F plane order": ("Si[(s * 3 + a) * NSC + t * 3 + b] += SIG[mu][nu][s][t] * Fh[a * 3 + b];",
+                            "Si[(s * 3 + a) * NSC + t * 3 + b] += SIG[nu][mu][s][t] * Fh[a * 3 + b];"),
 }
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_solver_pins.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -48,6 +60,6 @@ def test_pins_catch_mutation(name, tmp_path):
                    check=True)
     env = dict(os.environ, BQ_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        *[os.path.join(ROOT, "tests", f) for f in PIN_FILES]],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutation '{name}' survived the pins:\n{r.stdout[-2000:]}"
