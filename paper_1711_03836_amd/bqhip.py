@@ -45,7 +45,10 @@ BQ_F64, BQ_F32, BQ_F16 = 0, 1, 2
 BQ_EVEN, BQ_ODD, BQ_FULL = 0, 1, 2
 (BQ_OP_M, BQ_OP_MDAG, BQ_OP_MHAT, BQ_OP_MHATDAG, BQ_OP_MHATDAG_MHAT, BQ_OP_DEO, BQ_OP_DOE, BQ_OP_DEO_DAG,
  BQ_OP_DOE_DAG, BQ_OP_K1, BQ_OP_K1_DAG, BQ_OP_CLOVER, BQ_OP_CLOVER_INV, BQ_OP_MDAGM) = range(14)
-BQ_SYS_NORMAL, BQ_SYS_M, BQ_SYS_FULL_NORMAL = 0, 1, 2
+BQ_SYS_NORMAL, BQ_SYS_M, BQ_SYS_FULL_NORMAL, BQ_SYS_MHAT = 0, 1, 2, 3
+BQ_SOLVER_CG, BQ_SOLVER_BICGSTAB, BQ_SOLVER_BLOCK_CG = 0, 1, 2
+TRACE_TERMS = ("Minv", "Minv2", "g5Minv", "MdagMinv", "dkappa", "dcsw", "dmu")  # BQ_TR_* order
+BQ_TR_COUNT = len(TRACE_TERMS)
 
 OP_SUBSETS = {BQ_OP_M: (BQ_FULL, BQ_FULL), BQ_OP_MDAG: (BQ_FULL, BQ_FULL), BQ_OP_MDAGM: (BQ_FULL, BQ_FULL),
               BQ_OP_CLOVER: (BQ_FULL, BQ_FULL), BQ_OP_MHAT: (BQ_ODD, BQ_ODD), BQ_OP_MHATDAG: (BQ_ODD, BQ_ODD),
@@ -56,7 +59,7 @@ OP_SUBSETS = {BQ_OP_M: (BQ_FULL, BQ_FULL), BQ_OP_MDAG: (BQ_FULL, BQ_FULL), BQ_OP
 
 class bq_solve_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("inner_prec", C.c_int), ("delta", C.c_double),
-                ("system", C.c_int), ("chunk", C.c_int), ("use_graph", C.c_int)]
+                ("system", C.c_int), ("chunk", C.c_int), ("use_graph", C.c_int), ("solver", C.c_int)]
 
 
 class bq_solve_info(C.Structure):
@@ -83,14 +86,18 @@ class BqError(RuntimeError):
 
 _h = C.c_void_p
 _P = C.POINTER
+# caller device allocator: void* alloc(size_t bytes, void* ctx); void dealloc(void* ptr, void* ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 _sig = {
     "bq_version": (C.c_int, []),
     "bq_last_error": (C.c_char_p, []),
-    "bq_context_create": (C.c_int, [C.c_int, C.c_uint64, _P(_h)]),
+    "bq_context_create": (C.c_int, [C.c_int, C.c_uint64, ALLOC_FN, DEALLOC_FN, C.c_void_p, _P(_h)]),
     "bq_context_destroy": (C.c_int, [_h]),
     "bq_context_hbm_used": (C.c_int, [_h, _P(C.c_uint64)]),
     "bq_gauge_upload": (C.c_int, [_h, _P(C.c_int), C.c_void_p, C.c_int, C.c_int, _P(_h)]),
     "bq_gauge_plaquette": (C.c_int, [_h, _P(C.c_double)]),
+    "bq_gauge_su3_deviation": (C.c_int, [_h, _P(C.c_double)]),
     "bq_gauge_free": (C.c_int, [_h]),
     "bq_op_create": (C.c_int, [_h, C.c_double, C.c_double, C.c_double, _P(_h)]),
     "bq_op_free": (C.c_int, [_h]),
@@ -102,12 +109,18 @@ _sig = {
     "bq_solve": (C.c_int, [_h, _h, _h, _P(bq_solve_params), _P(bq_solve_info), C.c_void_p]),
     "bq_trace": (C.c_int, [_h, C.c_uint64, C.c_int, C.c_int, _P(bq_solve_params), _P(C.c_double), _P(C.c_double),
                            _P(bq_solve_info)]),
+    "bq_solve_multishift": (C.c_int, [_h, _h, C.c_int, _P(C.c_double), _P(_h), _P(bq_solve_params),
+                                      _P(bq_solve_info), C.c_void_p]),
+    "bq_trace_estimators": (C.c_int, [_h, C.c_uint64, C.c_int, C.c_int, _P(bq_solve_params), _P(C.c_double),
+                                      _P(bq_solve_info)]),
     "bq_solve_stats_get": (C.c_int, [_h, _P(bq_solve_stats)]),
     "bq_time_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_int, C.c_void_p, _P(C.c_double), _P(C.c_double)]),
     "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
     "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
     "bq_server_create": (C.c_int, [_h, C.c_int, C.c_int, _P(_h)]),
+    "bq_server_set_backfill": (C.c_int, [_h, C.c_int]),
+    "bq_server_release": (C.c_int, [_h, _h]),
     "bq_server_submit": (C.c_int, [_h, _h, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
                                    C.c_double, C.c_int, C.c_int, _P(C.c_uint64)]),
     "bq_server_step": (C.c_int, [_h, _P(C.c_uint64), C.c_int, _P(C.c_int)]),
@@ -141,6 +154,26 @@ def _ptr_of(a):
     return a.ctypes.data_as(C.c_void_p), 0
 
 
+def _order_after_torch(a, stream):
+    """For a torch device tensor and no explicit stream: order the library's work after the kernels that
+    produced (or are still to overwrite) `a` on torch's current stream.  The library orders itself
+    after a stream it is handed; torch's default stream has the handle 0, which the library reads as
+    "no stream", so that one is synchronized from the host instead."""
+    if stream is None and torch is not None and isinstance(a, torch.Tensor) and a.is_cuda:
+        cur = torch.cuda.current_stream(a.device)
+        if cur.cuda_stream == 0:
+            cur.synchronize()
+            return None
+        return cur
+    return stream
+
+
+def _check_tensor(a):
+    if torch is not None and isinstance(a, torch.Tensor):
+        if a.dtype != torch.complex128 or not a.is_contiguous():
+            raise ValueError("torch tensors in the canonical layout must be contiguous complex128")
+
+
 def _stream(stream):
     if stream is None:
         return None
@@ -154,9 +187,20 @@ def _stream(stream):
 # ---------------------------------------------------------------------------
 
 class Context:
-    def __init__(self, device=0, hbm_budget=0):
+    def __init__(self, device=0, hbm_budget=0, alloc=None, dealloc=None):
+        """alloc(nbytes) -> device pointer (int) and dealloc(ptr): an optional device allocator of the
+        caller (e.g. torch.cuda.caching_allocator_alloc / caching_allocator_delete) through which the
+        context takes all of its device memory."""
         h = _h()
-        check(bq_context_create(int(device), int(hbm_budget), C.byref(h)))
+        if (alloc is None) != (dealloc is None):
+            raise ValueError("give both alloc and dealloc, or neither")
+        if alloc is not None:
+            # the ctypes callbacks must live as long as the context
+            self._afn = ALLOC_FN(lambda n, _ctx: int(alloc(int(n))) or None)
+            self._dfn = DEALLOC_FN(lambda p, _ctx: dealloc(int(p)))
+        else:
+            self._afn, self._dfn = ALLOC_FN(), DEALLOC_FN()
+        check(bq_context_create(int(device), int(hbm_budget), self._afn, self._dfn, None, C.byref(h)))
         self.h = h
 
     def hbm_used(self):
@@ -208,14 +252,23 @@ class Gauge:
         self.ctx, self.dims = ctx, tuple(int(d) for d in dims)
         if not (torch is not None and isinstance(links, torch.Tensor)):
             links = np.ascontiguousarray(links, dtype=np.complex128)
+        _check_tensor(links)
+        if torch is not None and isinstance(links, torch.Tensor) and links.is_cuda:
+            torch.cuda.current_stream(links.device).synchronize()  # the upload reads on the library's stream
         p, dev = _ptr_of(links)
         h = _h()
         check(bq_gauge_upload(ctx.h, _dims(dims), p, dev, int(t_bc), C.byref(h)))
         self.h = h
+        self._close_pending = False
 
     def plaquette(self):
         v = C.c_double()
         check(bq_gauge_plaquette(self.h, C.byref(v)))
+        return v.value
+
+    def su3_deviation(self):
+        v = C.c_double()
+        check(bq_gauge_su3_deviation(self.h, C.byref(v)))
         return v.value
 
     def close(self):
@@ -223,9 +276,21 @@ class Gauge:
             check(bq_gauge_free(self.h))
             self.h = None
 
+    def _retry_close(self):
+        """Called when an operator or server that used this field lets go of it."""
+        if getattr(self, "_close_pending", False) and self.h:
+            try:
+                self.close()
+            except BqError:
+                pass
+
     def __del__(self):
+        # finalized while operators or server sessions still use the field (a reference cycle
+        # collected in arbitrary order): those free it when they close
         try:
             self.close()
+        except BqError as e:
+            self._close_pending = e.code == BQ_ERR_BUSY
         except Exception:
             pass
 
@@ -247,9 +312,9 @@ class Op:
         return ms.value, by.value
 
     def solve(self, b, x, tol, system=BQ_SYS_NORMAL, inner_prec=BQ_F64, maxiter=100000, delta=0.0, chunk=4,
-              use_graph=False, stream=None, raise_on_error=True):
+              use_graph=False, stream=None, raise_on_error=True, solver=BQ_SOLVER_CG):
         prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), float(delta), int(system), int(chunk),
-                              int(bool(use_graph)))
+                              int(bool(use_graph)), int(solver))
         info = (bq_solve_info * b.nrhs)()
         rc = bq_solve(self.h, b.h, x.h, C.byref(prm), info, _stream(stream))
         if raise_on_error and rc != BQ_OK:
@@ -267,6 +332,32 @@ class Op:
         a2 = np.frombuffer(t2, dtype=np.float64).copy()
         return a1[0::2] + 1j * a1[1::2], a2[0::2] + 1j * a2[1::2], [i.as_dict() for i in info]
 
+    def solve_multishift(self, b, xs, shifts, tol, maxiter=100000, chunk=8, stream=None, raise_on_error=True):
+        """(A + shifts[k]) xs[k] = b, A = Mhat^dag Mhat on odd sites; returns (rc, info[k][col])."""
+        n = len(shifts)
+        if len(xs) != n:
+            raise ValueError("one solution field per shift")
+        prm = bq_solve_params(float(tol), int(maxiter), BQ_F64, 0.0, BQ_SYS_NORMAL, int(chunk), 0)
+        sh = (C.c_double * n)(*[float(v) for v in shifts])
+        hx = (_h * n)(*[f.h for f in xs])
+        info = (bq_solve_info * (n * b.nrhs))()
+        rc = bq_solve_multishift(self.h, b.h, n, sh, hx, C.byref(prm), info, _stream(stream))
+        if raise_on_error and rc != BQ_OK:
+            check(rc)
+        flat = [i.as_dict() for i in info]
+        return rc, [flat[k * b.nrhs:(k + 1) * b.nrhs] for k in range(n)]
+
+    def trace_estimators(self, seed, nnoise, block, tol, inner_prec=BQ_F32, maxiter=100000, chunk=4):
+        """Per-noise terms of every BQ_TR_* estimator: dict name -> complex array (nnoise,), and info."""
+        prm = bq_solve_params(float(tol), int(maxiter), int(inner_prec), 0.0, BQ_SYS_M, int(chunk), 0)
+        est = (C.c_double * (2 * BQ_TR_COUNT * nnoise))()
+        info = (bq_solve_info * (2 * nnoise))()
+        check(bq_trace_estimators(self.h, C.c_uint64(seed & (2**64 - 1)), int(nnoise), int(block), C.byref(prm),
+                                  est, info))
+        a = np.frombuffer(est, dtype=np.float64).reshape(nnoise, BQ_TR_COUNT, 2)
+        z = a[..., 0] + 1j * a[..., 1]
+        return {name: z[:, k].copy() for k, name in enumerate(TRACE_TERMS)}, [i.as_dict() for i in info]
+
     def stats(self):
         st = bq_solve_stats()
         check(bq_solve_stats_get(self.h, C.byref(st)))
@@ -279,6 +370,7 @@ class Op:
         if self.h:
             check(bq_op_free(self.h))
             self.h = None
+            self.gauge._retry_close()
 
     def __del__(self):
         try:
@@ -302,15 +394,19 @@ class Field:
             a = np.ascontiguousarray(a, dtype=np.complex128)
         if tuple(a.shape) != (self.nrhs, self.V, 4, 3):
             raise ValueError(f"expected shape {(self.nrhs, self.V, 4, 3)}, got {tuple(a.shape)}")
+        _check_tensor(a)
         p, dev = _ptr_of(a)
-        check(bq_field_put(self.h, p, dev, _stream(stream)))
+        check(bq_field_put(self.h, p, dev, _stream(_order_after_torch(a, stream))))
 
     def get(self, out=None, stream=None):
         """Return (nrhs, V, 4, 3) complex128; sites outside the field's subset are zero (or kept from `out`)."""
         if out is None:
             out = np.zeros((self.nrhs, self.V, 4, 3), dtype=np.complex128)
+        if tuple(out.shape) != (self.nrhs, self.V, 4, 3):
+            raise ValueError(f"expected shape {(self.nrhs, self.V, 4, 3)}, got {tuple(out.shape)}")
+        _check_tensor(out)
         p, dev = _ptr_of(out)
-        check(bq_field_get(self.h, p, dev, _stream(stream)))
+        check(bq_field_get(self.h, p, dev, _stream(_order_after_torch(out, stream))))
         return out
 
     def close(self):
@@ -334,6 +430,7 @@ class Server:
         check(bq_server_create(ctx.h, int(slots), int(chunk), C.byref(h)))
         self.h = h
         self._keep = {}  # ticket -> (gauge, b, x): kept alive until retirement
+        self._gauges = {}  # gauge fields the server's sessions may hold
 
     def submit(self, gauge: Gauge, b, kappa, csw, mu=0.0, tol=1e-10, inner_prec=BQ_F32, maxiter=100000):
         """b: (nrhs, V, 4, 3) complex128, numpy (host) or a contiguous torch tensor (host or device);
@@ -353,6 +450,7 @@ class Server:
         check(bq_server_submit(self.h, gauge.h, float(kappa), float(csw), float(mu), bp, xp, b.shape[0], float(tol),
                                int(inner_prec), int(maxiter), C.byref(t)))
         self._keep[t.value] = (gauge, b, x)
+        self._gauges[id(gauge)] = gauge
         return t.value
 
     def step(self, max_done=4096):
@@ -376,10 +474,20 @@ class Server:
         check(bq_server_pending(self.h, C.byref(q), C.byref(r)))
         return q.value, r.value
 
+    def set_backfill(self, steps):
+        check(bq_server_set_backfill(self.h, int(steps)))
+
+    def release(self, gauge: Gauge):
+        check(bq_server_release(self.h, gauge.h))
+        self._gauges.pop(id(gauge), None)
+
     def close(self):
         if self.h:
             check(bq_server_free(self.h))
             self.h = None
+            for g in self._gauges.values():
+                g._retry_close()
+            self._gauges = {}
 
     def __del__(self):
         try:

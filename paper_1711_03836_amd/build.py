@@ -1,7 +1,8 @@
 """Build the HIP library libbqhip.so (gfx950) in-tree with hipcc.
 
-Each .hip translation unit under csrc/ is compiled to an object in parallel,
-then linked into paper_1711_03836_amd/libbqhip.so.  Every build recompiles.
+Each translation unit under csrc/ is compiled to an object in parallel (the
+stencil once per storage precision and columns per thread), then linked into
+paper_1711_03836_amd/libbqhip.so.  Every build recompiles.
 """
 from __future__ import annotations
 
@@ -27,13 +28,18 @@ FLAGS = [
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),
 ]
 
-SOURCES = ["bq_dslash_f64.hip", "bq_dslash_f32.hip", "bq_dslash_f16.hip", "bq_clover.hip", "bq_blas.hip",
-           "bq_api.hip"]
+# (source, object, extra defines): the stencil is compiled once per (storage precision, columns
+# per thread) so that its variants build in parallel
+STENCIL_R = {0: (1, 2), 1: (1, 2, 3, 4), 2: (1, 2, 3, 4)}
+UNITS = [("bq_dslash_inst.hip", f"bq_dslash_p{p}_r{r}.o", [f"-DBQ_INST_PREC={p}", f"-DBQ_INST_R={r}"])
+         for p, rs in STENCIL_R.items() for r in rs]
+UNITS += [(s, s.replace(".hip", ".o"), []) for s in ("bq_clover.hip", "bq_blas.hip", "bq_krylov.hip", "bq_api.hip")]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, verbose: bool) -> str:
+    src, objname, defs = unit
+    obj = os.path.join(BUILD, objname)
+    cmd = [HIPCC, *FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,9 +53,9 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
+    jobs = jobs or min(len(UNITS), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda u: _compile(u, verbose), UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
            "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"]

@@ -26,18 +26,29 @@
 #include "bqhip.h"
 
 namespace bq {
-hipError_t launch_hop_f64(const HopLaunch& L, hipStream_t st);
-hipError_t launch_hop_f32(const HopLaunch& L, hipStream_t st);
-hipError_t launch_hop_f16(const HopLaunch& L, hipStream_t st);
+// stencil instantiations, one per (storage precision, columns per thread): bq_dslash_inst.hip
+hipError_t launch_hop_p0_r1(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p0_r2(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p1_r1(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p1_r2(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p1_r3(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p1_r4(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p2_r1(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p2_r2(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p2_r3(const HopLaunch& L, hipStream_t st);
+hipError_t launch_hop_p2_r4(const HopLaunch& L, hipStream_t st);
 
 hipError_t launch_hop(const HopLaunch& L, hipStream_t st)
 {
-    switch (L.prec) {
-    case PREC_F64: return L.rprec == PREC_F64 ? launch_hop_f64(L, st) : hipErrorInvalidValue;
-    case PREC_F32: return L.rprec == PREC_F32 ? launch_hop_f32(L, st) : hipErrorInvalidValue;
-    case PREC_F16: return L.rprec == PREC_F32 ? launch_hop_f16(L, st) : hipErrorInvalidValue;
-    }
-    return hipErrorInvalidValue;
+    typedef hipError_t (*Fn)(const HopLaunch&, hipStream_t);
+    static const Fn tab[3][4] = {{launch_hop_p0_r1, launch_hop_p0_r2, nullptr, nullptr},
+                                 {launch_hop_p1_r1, launch_hop_p1_r2, launch_hop_p1_r3, launch_hop_p1_r4},
+                                 {launch_hop_p2_r1, launch_hop_p2_r2, launch_hop_p2_r3, launch_hop_p2_r4}};
+    // FP64 storage keeps an FP64 residual, FP32 and FP16 storage an FP32 one
+    const int want_rprec = L.prec == PREC_F64 ? PREC_F64 : PREC_F32;
+    if (L.prec < PREC_F64 || L.prec > PREC_F16 || L.rprec != want_rprec || L.R < 1 || L.R > 4) return hipErrorInvalidValue;
+    const Fn f = tab[L.prec][L.R - 1];
+    return f ? f(L, st) : hipErrorInvalidValue;
 }
 
 bool hop_variant_exists(int prec, int rprec, int recon, int R, int epi)
@@ -100,7 +111,22 @@ struct bq_context_s {
     hipStream_t stream = nullptr;
     std::map<std::pair<int, int>, Tune> tune;  // (prec, ncol) -> config
     unsigned nalloc = 0;                       // allocation counter (skews)
+    bq_alloc_fn alloc = nullptr;               // caller's device allocator (NULL: hipMalloc / hipFree)
+    bq_dealloc_fn dealloc = nullptr;
+    void* alloc_ctx = nullptr;
+    int nhandles = 0;        // live gauge fields, fields and servers created on this context
+    bool closing = false;    // bq_context_destroy was called while handles were alive
 };
+
+// A context whose destroy call came while handles were alive is freed with its last handle.
+static void ctx_release_handle(bq_context ctx)
+{
+    if (--ctx->nhandles == 0 && ctx->closing) {
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+    }
+}
 
 // Every array is laid out with its own small skew (an odd number of 128-byte lines): the
 // fields, link and clover arrays have power-of-two sizes on power-of-two lattices, and
@@ -119,7 +145,14 @@ struct DevBuf {
     void release()
     {
         if (raw) {
-            (void)hipFree(raw);
+            if (ctx->dealloc) {
+                // a caller's allocator may hand the block out again at once: finish the work
+                // queued on it first (hipFree synchronizes the same way)
+                (void)hipDeviceSynchronize();
+                ctx->dealloc(raw, ctx->alloc_ctx);
+            } else {
+                (void)hipFree(raw);
+            }
             ctx->used -= bytes;
         }
         raw = p = nullptr;
@@ -135,10 +168,21 @@ struct DevBuf {
         if (c->used + total > c->budget)
             return fail(BQ_ERR_OOM, "HBM budget exceeded: %zu bytes requested, %llu of %llu in use", total,
                         (unsigned long long)c->used, (unsigned long long)c->budget);
-        hipError_t e = hipMalloc(&raw, total);
-        if (e != hipSuccess) {
-            raw = nullptr;
-            return fail(BQ_ERR_OOM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+        hipError_t e = hipSuccess;
+        if (c->alloc) {
+            raw = c->alloc(total, c->alloc_ctx);
+            if (!raw) return fail(BQ_ERR_OOM, "the caller's allocator returned NULL for %zu bytes", total);
+            if (((uintptr_t)raw & 255u) != 0) {
+                c->dealloc(raw, c->alloc_ctx);
+                raw = nullptr;
+                return fail(BQ_ERR_INVALID, "the caller's allocator returned a block not aligned to 256 bytes");
+            }
+        } else {
+            e = hipMalloc(&raw, total);
+            if (e != hipSuccess) {
+                raw = nullptr;
+                return fail(BQ_ERR_OOM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+            }
         }
         // zero on the context stream and wait, so that work on any stream sees zeros
         e = hipMemsetAsync(raw, 0, total, c->stream);
@@ -159,6 +203,10 @@ static size_t col_pad_scales() { return kSkew / sizeof(float); }
 static int spinor_nu(int prec) { return prec == PREC_F16 ? 6 : 12; }
 static int clover_nu(int prec) { return prec == PREC_F16 ? 18 : 36; }
 static int link_nu(int prec, int recon) { return (recon == 18 ? 9 : 6) / (prec == PREC_F16 ? 2 : 1); }
+
+// largest distance from SU(3) (see bq_gauge_s::su3_dev) for which the two-row link form is
+// kept in storage precision prec: far below that precision's rounding of the links
+static double su3_tolerance(int prec) { return prec == PREC_F64 ? 1e-13 : (prec == PREC_F32 ? 1e-6 : 1e-3); }
 
 static bool dims_ok(const int* d)
 {
@@ -226,8 +274,10 @@ struct bq_gauge_s {
     Geom g{};
     int t_bc = -1;
     int nops = 0;
-    LinkSet links[5];  // F64/18, F64/12, F32/18, F32/12, F16/12
+    LinkSet links[5];  // F64/18, F64/12, F32/18, F32/12, F16/12 (two-row forms only where the links are SU(3))
     DevBuf B[2];       // kappa-independent clover field sum sigma (x) F per parity (built on first use)
+    double su3_dev = 0;  // max over links of max(|U U^dag - 1|, |det U - 1|), measured at upload
+    int nsess = 0;       // server sessions that hold this gauge field
     const LinkSet* get(int prec, int recon) const
     {
         for (const auto& l : links)
@@ -345,7 +395,8 @@ static HopLaunch hop_base(bq_op op, int prec, const Tune& t, int dagger, int out
     const bq_gauge G = op->gauge;
     L.prec = prec;
     L.rprec = prec == PREC_F64 ? PREC_F64 : PREC_F32;
-    L.recon = t.recon;
+    // two-row links exist only for SU(3) fields (bq_gauge_upload); FP64/FP32 fall back to 18 reals
+    L.recon = (t.recon == 12 && prec != PREC_F16 && !G->get(prec, 12)) ? 18 : t.recon;
     L.R = std::min(t.R, std::max(ncol, 1));
     L.bs = t.bs;
     L.march = (t.march > 0 && G->g.blocked && G->g.L[3] % t.march == 0) ? t.march : 0;
@@ -353,7 +404,7 @@ static HopLaunch hop_base(bq_op op, int prec, const Tune& t, int dagger, int out
     L.g = G->g;
     L.parity = out_parity;
     L.ncol = ncol;
-    const LinkSet* ls = G->get(prec, t.recon);
+    const LinkSet* ls = G->get(prec, L.recon);
     for (int k = 0; k < 8; k++) L.U[k] = ls ? ls->U[k] : nullptr;
     const double ep = std::exp(op->mu), em = std::exp(-op->mu);
     L.ef = dagger ? em : ep;
@@ -365,7 +416,10 @@ static HopLaunch hop_base(bq_op op, int prec, const Tune& t, int dagger, int out
 static int run_hop(const HopLaunch& L, hipStream_t st)
 {
     for (int k = 0; k < 8; k++)
-        if (!L.U[k]) return fail(BQ_ERR_UNSUPPORTED, "no link copy for precision %d / recon %d", L.prec, L.recon);
+        if (!L.U[k])
+            return fail(BQ_ERR_UNSUPPORTED,
+                        "no %d-real link copy in precision %d: the gauge field is not SU(3) to that precision "
+                        "(FP16 storage and per-column operators need the two-row form)", L.recon, L.prec);
     hipError_t e = launch_hop(L, st);
     if (e != hipSuccess)
         return fail(e == hipErrorInvalidValue ? BQ_ERR_UNSUPPORTED : BQ_ERR_DEVICE,
@@ -491,6 +545,25 @@ static int hopv(const OpCall& c, int dag, int parity, FieldArg in, FieldArg out,
     L.status = c.status;
     L.statmask = c.statmask;
     apply_cols(c, L, parity, false, fk);
+    return run_hop(L, c.st);
+}
+
+// out_p = a v_p + f D' in with D' the hopping term whose time hops carry the factors ef (forward)
+// and eb (backward) instead of e^{+-mu}; the time-boundary sign still applies
+static int hop_coef(const OpCall& c, int parity, FieldArg in, FieldArg out, FieldArg v, double a, double f, double ef,
+                    double eb)
+{
+    HopLaunch L = hop_base(c.op, c.prec, c.t, 0, parity, c.ncol);
+    L.epi = EPI_HOP;
+    L.in = in;
+    L.out = out;
+    L.v = v;
+    L.a = a;
+    L.f = f;
+    L.ef = ef;
+    L.eb = eb;
+    L.status = c.status;
+    L.statmask = c.statmask;
     return run_hop(L, c.st);
 }
 
@@ -874,6 +947,10 @@ static int solve_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec&
     }
     if (sys == BQ_SYS_NORMAL) {
         HIPCHK(launch_convert(PREC_F64, b_odd.all(), PREC_F64, w->bp.all(), b_odd.sites(), ncol, nullptr, 0, st));
+    } else if (sys == BQ_SYS_MHAT) {
+        // b' = Mhat^dag b
+        CHK(k1(c64, 1, b_odd.all(), w->t64.all()));
+        CHK(tv(c64, 1, 1, w->t64.all(), b_odd.all(), w->bp.all(), -kap * kap, nullptr, hw, hw));
     } else if (sys == BQ_SYS_FULL_NORMAL) {
         HIPCHK(launch_convert(PREC_F64, b_even.all(), PREC_F64, w->bp.half(0), (int)b_even.half_sites, ncol, nullptr, 0, st));
         HIPCHK(launch_convert(PREC_F64, b_odd.all(), PREC_F64, w->bp.half(1), (int)b_odd.half_sites, ncol, nullptr, 0, st));
@@ -913,6 +990,14 @@ static int solve_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec&
     std::vector<double> fr2(ncol, 0.0), fb2(ncol, 1.0);
     if (sys == BQ_SYS_NORMAL) {
         HIPCHK(launch_convert(PREC_F64, w->x.all(), PREC_F64, x_odd.all(), x_odd.sites(), ncol, nullptr, 0, st));
+    } else if (sys == BQ_SYS_MHAT) {
+        HIPCHK(launch_convert(PREC_F64, w->x.all(), PREC_F64, x_odd.all(), x_odd.sites(), ncol, nullptr, 0, st));
+        // |b - Mhat x|^2 (r serves as scratch)
+        CHK(k1(c64, 0, x_odd.all(), w->t64.all()));
+        CHK(tvr(c64, 0, 1, w->t64.all(), x_odd.all(), b_odd.all(), w->r.all(), -kap * kap, nullptr, w->partial, hw, hw));
+        HIPCHK(launch_fin_sum(w->partial, hw, ncol, w->dtmp, st));
+        HIPCHK(hipMemcpyAsync(fr2.data(), w->dtmp, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        CHK(norms(op, w, b_odd, ncol, fb2, st));
     } else if (sys == BQ_SYS_FULL_NORMAL) {
         HIPCHK(launch_convert(PREC_F64, w->x.half(0), PREC_F64, x_even.all(), (int)x_even.half_sites, ncol, nullptr, 0, st));
         HIPCHK(launch_convert(PREC_F64, w->x.half(1), PREC_F64, x_odd.all(), (int)x_odd.half_sites, ncol, nullptr, 0, st));
@@ -935,7 +1020,7 @@ static int solve_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec&
     int rc = BQ_OK;
     for (int col = 0; col < ncol; col++) {
         const double tr = b2[col] > 0 ? std::sqrt(r2[col] / b2[col]) : 0.0;
-        const double fr = sys == BQ_SYS_M ? (fb2[col] > 0 ? std::sqrt(fr2[col] / fb2[col]) : 0.0) : tr;
+        const double fr = (sys == BQ_SYS_M || sys == BQ_SYS_MHAT) ? (fb2[col] > 0 ? std::sqrt(fr2[col] / fb2[col]) : 0.0) : tr;
         int cst = BQ_OK;
         if (!std::isfinite(tr) || status[col] == COL_FAILED)
             cst = (!std::isfinite(tr) || !std::isfinite(b2[col])) ? BQ_ERR_NONFINITE : BQ_ERR_NOT_CONVERGED;
@@ -958,6 +1043,204 @@ static int solve_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec&
 }
 
 // ---------------------------------------------------------------------------
+// BiCGstab on Mhat (the solver list's BiCGstab), van der Vorst's recursion per column in the
+// inner precision with FP64 reductions.  Mhat is not Hermitian at mu != 0, and BiCGstab works
+// on Mhat itself instead of the normal equations.  An inner run stops when its recursive
+// residual falls below delta times the last FP64 residual (or reaches tol |bhat|); the FP64
+// residual bhat - Mhat x is then recomputed, and the column is done or restarts from it.
+// ---------------------------------------------------------------------------
+
+static int bicg_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec& x_even, const Vec& x_odd, int ncol,
+                      const bq_solve_params& prm, bq_solve_info* info, hipStream_t st, SolveAcct& acct)
+{
+    const int sys = prm.system;
+    const int prec = prm.inner_prec;
+    bq_context ctx = op->gauge->ctx;
+    const Geom& g = op->gauge->g;
+    const double kap = op->kappa;
+    const int hw = pad_sites(g.Vh) / kTile;
+    // workspace: FP64 bhat, x64, r64, odd q64 and even t64 scratch; inner r, rhat, p, v, s, t, even te, x
+    DevBuf d[16], sc[16];
+    Vec bh, x64, r64, q64, t64, r, rh, p, v, s_, t, te, xi;
+    int k = 0;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[k], sc[k], bh)); k++;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[k], sc[k], x64)); k++;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[k], sc[k], r64)); k++;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[k], sc[k], q64)); k++;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[k], sc[k], t64)); k++;
+    for (Vec* vv : {&r, &rh, &p, &v, &s_, &t, &te}) {
+        CHK(alloc_vec(ctx, g, prec, 1, ncol, d[k], sc[k], *vv));
+        k++;
+    }
+    if (prec == PREC_F64) xi = x64;
+    else CHK(alloc_vec(ctx, g, prec, 1, ncol, d[k], sc[k], xi));
+    const int n = (int)bh.half_sites;
+    DevBuf part, scal, ints;
+    CHK(part.alloc(ctx, sizeof(double) * (size_t)hw * ncol * 4));
+    CHK(scal.alloc(ctx, sizeof(double) * (size_t)ncol * 11));
+    CHK(ints.alloc(ctx, sizeof(int) * (size_t)ncol * 4));
+    double* pt = part.as<double>();
+    BicgScalars S{};
+    {
+        double* q = scal.as<double>();
+        S.rho = (double2*)q; S.alpha = (double2*)(q + 2 * ncol); S.omega = (double2*)(q + 4 * ncol);
+        S.beta = (double2*)(q + 6 * ncol); S.r2 = q + 8 * ncol; S.stop2 = q + 9 * ncol; S.tol2b2 = q + 10 * ncol;
+        int* i = ints.as<int>();
+        S.status = i; S.iters = i + ncol; S.nrel = i + 2 * ncol; S.restart = i + 3 * ncol;
+        const double delta = prm.delta > 0 ? prm.delta : (prec == PREC_F32 ? 0.01 : 0.0);
+        S.delta2 = delta * delta;
+    }
+    OpCall c64{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, nullptr, 1, st};
+    const double s64 = sp_bytes(PREC_F64), sP = sp_bytes(prec), Vh = g.Vh;
+    // bhat
+    if (sys == BQ_SYS_M) {
+        HIPCHK(launch_clover_apply(PREC_F64, g, op->Tinv[PREC_F64][0].p, b_even.all(), t64.all(), ncol, st));
+        CHK(hopv(c64, 0, 1, t64.all(), bh.all(), b_odd.all(), 1.0, kap));
+        acct.bytes += stencil_shared(op, PREC_F64) + ncol * Vh * 5 * s64;
+    } else {
+        HIPCHK(launch_convert(PREC_F64, b_odd.all(), PREC_F64, bh.all(), n, ncol, nullptr, 0, st));
+        acct.bytes += ncol * Vh * 2 * s64;
+    }
+    // start: x = 0, r64 = bhat, every column "stopped" so that the first reliable pass sets it up
+    std::vector<double> b2(ncol), t2(ncol);
+    HIPCHK(launch_norm2(PREC_F64, bh.all(), n, ncol, pt, hw, st));
+    HIPCHK(launch_fin_sum(pt, hw, ncol, S.r2, st));
+    HIPCHK(hipMemcpyAsync(b2.data(), S.r2, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int c = 0; c < ncol; c++) t2[c] = prm.tol * prm.tol * b2[c];
+    HIPCHK(hipMemcpyAsync(S.tol2b2, t2.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, st));
+    {
+        std::vector<int> z(4 * ncol, 0);
+        for (int c = 0; c < ncol; c++) z[c] = COL_STOPPED;
+        HIPCHK(hipMemcpyAsync(S.status, z.data(), sizeof(int) * 4 * ncol, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(launch_zero(PREC_F64, x64.all(), n, ncol, nullptr, 0, st));
+    HIPCHK(launch_convert(PREC_F64, bh.all(), PREC_F64, r64.all(), n, ncol, nullptr, 0, st));
+    const int mRestart = 1 << COL_JUST_STOPPED, mStopped = 1 << COL_STOPPED;
+    // decide / restart: partials of |r64|^2 are in pt
+    auto restart = [&]() -> int {
+        HIPCHK(launch_fin_bicg(3, S, pt, hw, ncol, st));
+        if (prec != PREC_F64) HIPCHK(launch_zero(prec, xi.all(), n, ncol, S.status, mRestart, st));
+        HIPCHK(launch_convert(PREC_F64, r64.all(), prec, r.all(), n, ncol, S.status, mRestart, st));
+        HIPCHK(launch_convert(prec, r.all(), prec, rh.all(), n, ncol, S.status, mRestart, st));
+        HIPCHK(launch_zero(prec, p.all(), n, ncol, S.status, mRestart, st));
+        HIPCHK(launch_zero(prec, v.all(), n, ncol, S.status, mRestart, st));
+        HIPCHK(launch_set_status(S.status, S.restart, ncol, COL_ACTIVE, st));
+        return BQ_OK;
+    };
+    HIPCHK(launch_norm2(PREC_F64, r64.all(), n, ncol, pt, hw, st));
+    CHK(restart());
+    const int kchunk = prm.chunk > 0 ? prm.chunk : 4;
+    const long maxiter = prm.maxiter > 0 ? prm.maxiter : 100000;
+    OpCall ci{op, prec, get_tune(ctx, prec, ncol), ncol, S.status, 1 << COL_ACTIVE, st};
+    OpCall cr{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, S.status, mStopped, st};
+    std::vector<int> hs(3 * ncol), prev(3 * ncol, 0);
+    long done = 0;
+    const double ishared = 4 * stencil_shared(op, prec), icol = Vh * 30 * sP;
+    const double rshared = 2 * stencil_shared(op, PREC_F64), rcol = Vh * (7 * s64 + (prec != PREC_F64 ? 2 * (s64 + sP) : 0));
+    while (true) {
+        for (int it = 0; it < kchunk; it++) {
+            HIPCHK(launch_bicg_p(prec, r.all(), p.all(), v.all(), S, n, ncol, st));
+            CHK(k1(ci, 0, p.all(), te.all()));
+            CHK(tv(ci, 0, 1, te.all(), p.all(), v.all(), -kap * kap, nullptr, hw, hw));
+            HIPCHK(launch_dots2(prec, rh.all(), v.all(), FieldArg(), FieldArg(), S.status, n, ncol, pt, hw, st));
+            HIPCHK(launch_fin_bicg(0, S, pt, hw, ncol, st));
+            HIPCHK(launch_bicg_s(prec, r.all(), v.all(), s_.all(), S, n, ncol, st));
+            CHK(k1(ci, 0, s_.all(), te.all()));
+            CHK(tv(ci, 0, 1, te.all(), s_.all(), t.all(), -kap * kap, nullptr, hw, hw));
+            HIPCHK(launch_dots2(prec, t.all(), s_.all(), t.all(), t.all(), S.status, n, ncol, pt, hw, st));
+            HIPCHK(launch_fin_bicg(1, S, pt, hw, ncol, st));
+            HIPCHK(launch_bicg_xr(prec, xi.all(), p.all(), s_.all(), t.all(), r.all(), rh.all(), S, n, ncol, pt, hw, st));
+            HIPCHK(launch_fin_bicg(2, S, pt, hw, ncol, st));
+        }
+        // reliable pass for the columns whose inner run stopped: x64 += x, r64 = bhat - Mhat x64
+        if (prec != PREC_F64) HIPCHK(launch_accum(prec, xi.all(), x64.all(), n, ncol, S.status, mStopped, st));
+        CHK(k1(cr, 0, x64.all(), t64.all()));
+        CHK(tvr(cr, 0, 1, t64.all(), x64.all(), bh.all(), r64.all(), -kap * kap, nullptr, pt, hw, hw));
+        CHK(restart());
+        done += kchunk;
+        acct.chunks++;
+        acct.iterations += kchunk;
+        acct.launches += 12L * kchunk + 9 + (prec != PREC_F64);
+        HIPCHK(hipMemcpyAsync(hs.data(), S.status, sizeof(int) * 3 * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int dmax = 0, nrel = 0;
+        double colit = 0;
+        for (int c = 0; c < ncol; c++) {
+            const int di = hs[ncol + c] - prev[ncol + c];
+            dmax = std::max(dmax, di);
+            colit += di;
+            nrel += hs[2 * ncol + c] - prev[2 * ncol + c];
+        }
+        acct.bytes += dmax * ishared + colit * icol + (nrel > 0 ? rshared + nrel * rcol : 0.0);
+        prev = hs;
+        bool all = true;
+        for (int c = 0; c < ncol; c++)
+            if (hs[c] != COL_DONE && hs[c] != COL_FAILED) all = false;
+        if (all || done >= maxiter) break;
+    }
+    // columns still iterating: fold the inner iterate
+    if (prec != PREC_F64)
+        HIPCHK(launch_accum(prec, xi.all(), x64.all(), n, ncol, S.status, (1 << COL_ACTIVE) | mStopped, st));
+    // final FP64 residual |bhat - Mhat x| for every column
+    CHK(k1(c64, 0, x64.all(), t64.all()));
+    CHK(tvr(c64, 0, 1, t64.all(), x64.all(), bh.all(), r64.all(), -kap * kap, nullptr, pt, hw, hw));
+    std::vector<double> r2(ncol), fr2(ncol, 0.0), fb2(ncol, 1.0);
+    HIPCHK(launch_fin_sum(pt, hw, ncol, S.r2, st));
+    HIPCHK(hipMemcpyAsync(r2.data(), S.r2, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_convert(PREC_F64, x64.all(), PREC_F64, x_odd.all(), n, ncol, nullptr, 0, st));
+    acct.bytes += rshared + ncol * Vh * 9 * s64;
+    if (sys == BQ_SYS_M) {
+        // x_e = T_ee^-1 (b_e + kappa D_eo x_o); |b - M x|^2 over both parities
+        CHK(k1(c64, 0, x_odd.all(), x_even.all(), b_even.all(), 1.0, kap));
+        CHK(tvr(c64, 0, 0, x_odd.all(), x_even.all(), b_even.all(), t64.all(), -kap, nullptr, pt, hw, 2 * hw));
+        CHK(tvr(c64, 0, 1, x_even.all(), x_odd.all(), b_odd.all(), q64.all(), -kap, nullptr, pt + hw, hw, 2 * hw));
+        HIPCHK(launch_fin_sum(pt, 2 * hw, ncol, S.r2, st));
+        HIPCHK(hipMemcpyAsync(fr2.data(), S.r2, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(launch_norm2(PREC_F64, b_even.all(), n, ncol, pt, hw, st));
+        HIPCHK(launch_norm2(PREC_F64, b_odd.all(), n, ncol, pt + (size_t)hw * ncol, hw, st));
+        HIPCHK(launch_fin_sum(pt, hw, 2 * ncol, S.stop2, st));
+        std::vector<double> be(2 * ncol);
+        HIPCHK(hipMemcpyAsync(be.data(), S.stop2, sizeof(double) * 2 * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int c = 0; c < ncol; c++) fb2[c] = be[c] + be[ncol + c];
+        acct.bytes += 3 * stencil_shared(op, PREC_F64) + ncol * Vh * 13 * s64;
+    }
+    std::vector<int> h(3 * ncol);
+    HIPCHK(hipMemcpyAsync(h.data(), S.status, sizeof(int) * 3 * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int rc = BQ_OK;
+    for (int c = 0; c < ncol; c++) {
+        const double tr = b2[c] > 0 ? std::sqrt(r2[c] / b2[c]) : 0.0;
+        const double fr = sys == BQ_SYS_M ? (fb2[c] > 0 ? std::sqrt(fr2[c] / fb2[c]) : 0.0) : tr;
+        int cst = BQ_OK;
+        if (!std::isfinite(tr)) cst = BQ_ERR_NONFINITE;
+        else if (h[c] == COL_FAILED || !(tr <= prm.tol)) cst = BQ_ERR_NOT_CONVERGED;
+        if (info) {
+            info[c].iters = h[ncol + c];
+            info[c].reliable_updates = std::max(0, h[2 * ncol + c] - 1);  // the first pass only sets up
+            info[c].true_rel_resid = tr;
+            info[c].full_rel_resid = fr;
+            info[c].converged = cst == BQ_OK;
+            info[c].status = cst;
+        }
+        if (cst == BQ_ERR_NONFINITE) rc = cst;
+        else if (cst != BQ_OK && rc == BQ_OK) rc = cst;
+    }
+    if (rc == BQ_ERR_NOT_CONVERGED) fail(rc, "some right-hand side did not converge within maxiter");
+    if (rc == BQ_ERR_NONFINITE) fail(rc, "non-finite value in the source or during the solve");
+    return rc;
+}
+
+static int bcg_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec& x_even, const Vec& x_odd, int ncol,
+                     const bq_solve_params& prm, bq_solve_info* info, hipStream_t st, SolveAcct& acct)
+{
+    (void)op; (void)b_even; (void)b_odd; (void)x_even; (void)x_odd; (void)ncol; (void)prm; (void)info; (void)st;
+    (void)acct;
+    return fail(BQ_ERR_UNSUPPORTED, "block CG is not available in this build");
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 
@@ -967,10 +1250,13 @@ int bq_version(void) { return 10000; }
 
 const char* bq_last_error(void) { return g_err.c_str(); }
 
-int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_context* out)
+int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_alloc_fn alloc, bq_dealloc_fn dealloc,
+                      void* alloc_ctx, bq_context* out)
 {
     if (!out) return fail(BQ_ERR_INVALID, "out is NULL");
     *out = nullptr;
+    if ((alloc == nullptr) != (dealloc == nullptr))
+        return fail(BQ_ERR_INVALID, "alloc and dealloc must both be given or both be NULL");
     int n = 0;
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(BQ_ERR_INVALID, "device %d out of range (%d devices)", device, n);
@@ -980,6 +1266,9 @@ int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_context* out)
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    c->alloc = alloc;
+    c->dealloc = dealloc;
+    c->alloc_ctx = alloc_ctx;
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     *out = c.release();
     return BQ_OK;
@@ -988,6 +1277,11 @@ int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_context* out)
 int bq_context_destroy(bq_context ctx)
 {
     if (!ctx) return BQ_OK;
+    if (ctx->closing) return fail(BQ_ERR_INVALID, "context already destroyed");
+    if (ctx->nhandles > 0) {  // freed together with its last handle
+        ctx->closing = true;
+        return BQ_OK;
+    }
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1023,10 +1317,29 @@ int bq_gauge_upload(bq_context ctx, const int dims[4], const double* links, int 
         HIPCHK(hipMemcpyAsync(stage.p, links, nbytes, hipMemcpyHostToDevice, ctx->stream));
         canon = stage.as<double2>();
     }
+    // The two-row link form rebuilds row 2 as conj(row0 x row1), which holds for SU(3) only: it is
+    // kept for a storage precision only if every link is SU(3) to well within that precision's
+    // rounding.  Without it FP64 and FP32 stencils read all 18 reals, and FP16 storage and the
+    // server (both two-row only) report BQ_ERR_UNSUPPORTED.
+    {
+        const size_t nl = 4 * V;
+        const int np = link_su3_parts(nl);
+        DevBuf part;
+        CHK(part.alloc(ctx, sizeof(double) * np));
+        HIPCHK(launch_link_su3_dev(canon, nl, part.as<double>(), ctx->stream));
+        std::vector<double> h(np);
+        HIPCHK(hipMemcpyAsync(h.data(), part.p, sizeof(double) * np, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        double d = 0;
+        for (double v : h) d = std::isnan(v) ? INFINITY : std::max(d, v);
+        G->su3_dev = d;
+        if (!std::isfinite(d)) return fail(BQ_ERR_NONFINITE, "non-finite gauge link");
+    }
     const int forms[5][2] = {{PREC_F64, 18}, {PREC_F64, 12}, {PREC_F32, 18}, {PREC_F32, 12}, {PREC_F16, 12}};
     const size_t Vp = pad_sites(G->g.Vh);
     for (int f = 0; f < 5; f++) {
         LinkSet& ls = G->links[f];
+        if (forms[f][1] == 12 && G->su3_dev > su3_tolerance(forms[f][0])) continue;
         ls.prec = forms[f][0];
         ls.recon = forms[f][1];
         const size_t per = Vp * link_nu(ls.prec, ls.recon) * unit_bytes(ls.prec) + kSkew;
@@ -1039,6 +1352,14 @@ int bq_gauge_upload(bq_context ctx, const int dims[4], const double* links, int 
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     *out = G.release();
+    ctx->nhandles++;
+    return BQ_OK;
+}
+
+int bq_gauge_su3_deviation(bq_gauge g, double* dev)
+{
+    if (!g || !dev) return fail(BQ_ERR_INVALID, "NULL argument");
+    *dev = g->su3_dev;
     return BQ_OK;
 }
 
@@ -1067,8 +1388,12 @@ int bq_gauge_free(bq_gauge g)
 {
     if (!g) return BQ_OK;
     if (g->nops > 0) return fail(BQ_ERR_BUSY, "%d operator(s) still use this gauge field", g->nops);
-    (void)hipSetDevice(g->ctx->device);
+    if (g->nsess > 0)
+        return fail(BQ_ERR_BUSY, "%d server session(s) still hold this gauge field (bq_server_release)", g->nsess);
+    bq_context ctx = g->ctx;
+    (void)hipSetDevice(ctx->device);
     delete g;
+    ctx_release_handle(ctx);
     return BQ_OK;
 }
 
@@ -1177,14 +1502,17 @@ int bq_field_create(bq_context ctx, const int dims[4], int subset, int prec, int
     CHK(f->data.alloc(ctx, f->cstride * nrhs * unit_bytes(prec)));
     if (prec == BQ_F16) CHK(f->scale.alloc(ctx, f->sstride * nrhs * sizeof(float)));
     *out = f.release();
+    ctx->nhandles++;
     return BQ_OK;
 }
 
 int bq_field_free(bq_field f)
 {
     if (!f) return BQ_OK;
-    (void)hipSetDevice(f->ctx->device);
+    bq_context ctx = f->ctx;
+    (void)hipSetDevice(ctx->device);
     delete f;
+    ctx_release_handle(ctx);
     return BQ_OK;
 }
 
@@ -1243,6 +1571,12 @@ int bq_field_get(bq_field f, double* dst, int dst_on_device, void* stream)
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return BQ_OK;
 }
+
+// fields the library creates for its own use are released through the ABI call (handle count)
+struct FieldFree {
+    void operator()(bq_field f) const { (void)bq_field_free(f); }
+};
+using FieldPtr = std::unique_ptr<bq_field_s, FieldFree>;
 
 // required subsets per kind: {in, out}
 static bool kind_subsets(int kind, int* in, int* out)
@@ -1404,16 +1738,34 @@ int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void*
     return BQ_OK;
 }
 
+// the checks every solver entry point applies to its parameters
+static int check_solve_params(const bq_solve_params& p)
+{
+    if (!(p.tol > 0) || !std::isfinite(p.tol)) return fail(BQ_ERR_INVALID, "tol must be > 0");
+    if (p.inner_prec < BQ_F64 || p.inner_prec > BQ_F16) return fail(BQ_ERR_INVALID, "bad inner precision");
+    if (p.system < BQ_SYS_NORMAL || p.system > BQ_SYS_MHAT) return fail(BQ_ERR_INVALID, "bad system");
+    if (p.solver < BQ_SOLVER_CG || p.solver > BQ_SOLVER_BLOCK_CG) return fail(BQ_ERR_INVALID, "bad solver");
+    if (p.system == BQ_SYS_FULL_NORMAL && (p.inner_prec != BQ_F64 || p.solver != BQ_SOLVER_CG))
+        return fail(BQ_ERR_UNSUPPORTED, "the unpreconditioned system is solved by FP64 CG only");
+    if (p.solver == BQ_SOLVER_BICGSTAB) {
+        if (p.system != BQ_SYS_M && p.system != BQ_SYS_MHAT)
+            return fail(BQ_ERR_UNSUPPORTED, "BiCGstab solves M x = b (BQ_SYS_M) or Mhat x = b (BQ_SYS_MHAT)");
+        if (p.inner_prec == BQ_F16) return fail(BQ_ERR_UNSUPPORTED, "BiCGstab iterates in FP64 or FP32");
+    }
+    if (p.solver == BQ_SOLVER_BLOCK_CG && p.inner_prec != BQ_F64)
+        return fail(BQ_ERR_UNSUPPORTED, "block CG iterates in FP64");
+    if (p.solver != BQ_SOLVER_CG && p.use_graph) return fail(BQ_ERR_UNSUPPORTED, "graph capture is for CG only");
+    if (p.maxiter < 0 || p.chunk < 0 || !(p.delta >= 0) || !(p.delta < 1))
+        return fail(BQ_ERR_INVALID, "maxiter and chunk must be >= 0 and delta in [0, 1)");
+    return BQ_OK;
+}
+
 int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq_solve_info* info, void* stream)
 {
     if (!op || !b || !x || !params) return fail(BQ_ERR_INVALID, "NULL argument");
     const bq_solve_params& p = *params;
-    if (!(p.tol > 0) || !std::isfinite(p.tol)) return fail(BQ_ERR_INVALID, "tol must be > 0");
-    if (p.inner_prec < BQ_F64 || p.inner_prec > BQ_F16) return fail(BQ_ERR_INVALID, "bad inner precision");
-    if (p.system < BQ_SYS_NORMAL || p.system > BQ_SYS_FULL_NORMAL) return fail(BQ_ERR_INVALID, "bad system");
-    if (p.system == BQ_SYS_FULL_NORMAL && p.inner_prec != BQ_F64)
-        return fail(BQ_ERR_UNSUPPORTED, "the unpreconditioned system is solved in FP64 only");
-    const int want = p.system == BQ_SYS_NORMAL ? BQ_ODD : BQ_FULL;
+    CHK(check_solve_params(p));
+    const int want = (p.system == BQ_SYS_NORMAL || p.system == BQ_SYS_MHAT) ? BQ_ODD : BQ_FULL;
     if (b->subset != want || x->subset != want) return fail(BQ_ERR_INVALID, "b and x must be %s fields", want == BQ_ODD ? "ODD" : "FULL");
     if (b->prec != BQ_F64 || x->prec != BQ_F64) return fail(BQ_ERR_INVALID, "b and x must be FP64 fields");
     if (b->nrhs != x->nrhs) return fail(BQ_ERR_INVALID, "b and x have different nrhs");
@@ -1439,7 +1791,13 @@ int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, ctx->stream));
-    const int rc = solve_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
+    int rc;
+    if (p.solver == BQ_SOLVER_BICGSTAB)
+        rc = bicg_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
+    else if (p.solver == BQ_SOLVER_BLOCK_CG)
+        rc = bcg_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
+    else
+        rc = solve_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
     HIPCHK(hipEventRecord(e1, ctx->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
@@ -1452,6 +1810,208 @@ int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq
     op->last.chunks = acct.chunks;
     op->last.iterations = acct.iterations;
     return rc;
+}
+
+// Multishift CG (the solver list's "multishift cg", the RHMC solver): all shifts share the Krylov
+// space of the base system A + sigma_b, sigma_b the smallest shift; shifted residuals stay
+// collinear with the base residual, r_k = zeta_k r, and each shift's solution and direction are
+// updated with its own alpha_k, beta_k from the zeta recurrence (Jegerlehner's shifted CG).
+// One M-hat-dagger-M-hat application per iteration serves every shift and every column.
+int bq_solve_multishift(bq_op op, bq_field b, int nshift, const double* shifts, bq_field* x,
+                        const bq_solve_params* params, bq_solve_info* info, void* stream)
+{
+    if (!op || !b || !shifts || !x || !params) return fail(BQ_ERR_INVALID, "NULL argument");
+    const bq_solve_params& prm = *params;
+    CHK(check_solve_params(prm));
+    if (prm.system != BQ_SYS_NORMAL) return fail(BQ_ERR_INVALID, "multishift CG solves Mhat^dag Mhat + sigma (BQ_SYS_NORMAL)");
+    if (prm.inner_prec != BQ_F64) return fail(BQ_ERR_UNSUPPORTED, "multishift CG runs in FP64");
+    if (nshift < 1 || nshift > kMaxShifts) return fail(BQ_ERR_INVALID, "nshift must be in 1..%d", kMaxShifts);
+    int base = 0;
+    for (int k = 0; k < nshift; k++) {
+        if (!std::isfinite(shifts[k]) || shifts[k] < 0) return fail(BQ_ERR_INVALID, "shifts must be finite and >= 0");
+        if (shifts[k] < shifts[base]) base = k;
+    }
+    if (b->subset != BQ_ODD || b->prec != BQ_F64) return fail(BQ_ERR_INVALID, "b must be an ODD FP64 field");
+    for (int k = 0; k < nshift; k++) {
+        if (!x[k] || x[k]->subset != BQ_ODD || x[k]->prec != BQ_F64 || x[k]->nrhs != b->nrhs || x[k] == b)
+            return fail(BQ_ERR_INVALID, "x[%d] must be an ODD FP64 field with b's nrhs, other than b", k);
+        for (int q = 0; q < k; q++)
+            if (x[q] == x[k]) return fail(BQ_ERR_INVALID, "x[%d] and x[%d] are the same field", q, k);
+        for (int m = 0; m < 4; m++)
+            if (x[k]->dims[m] != op->gauge->dims[m]) return fail(BQ_ERR_INVALID, "field and gauge lattices differ");
+    }
+    for (int m = 0; m < 4; m++)
+        if (b->dims[m] != op->gauge->dims[m]) return fail(BQ_ERR_INVALID, "field and gauge lattices differ");
+    bq_context ctx = op->gauge->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    CHK(sync_with(ctx, (hipStream_t)stream));
+    hipStream_t st = ctx->stream;
+    const Geom& g = op->gauge->g;
+    const int ncol = b->nrhs;
+    const double sb = shifts[base], kap = op->kappa;
+
+    // workspace: r, p, w, q (odd), t (even), a direction per shift other than the base
+    DevBuf dr, sr, dp, spp, dw, sw, dq, sq, dt, stt;
+    Vec r, p, w, q, t;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dr, sr, r));
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dp, spp, p));
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dw, sw, w));
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dq, sq, q));
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dt, stt, t));
+    std::vector<std::unique_ptr<DevBuf>> pkbuf;
+    MsFields f{};
+    f.r = r.all();
+    f.w = w.all();
+    f.p = p.all();
+    for (int k = 0; k < nshift; k++) {
+        f.x[k] = parity_vec(x[k], 1).all();
+        if (k == base) {
+            f.pk[k] = p.all();
+            continue;
+        }
+        pkbuf.emplace_back(new DevBuf);
+        DevBuf dummy;
+        Vec v;
+        CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, *pkbuf.back(), dummy, v));
+        f.pk[k] = v.all();
+    }
+    const int hw = pad_sites(g.Vh) / kTile;
+    const int n = (int)r.half_sites;
+    DevBuf part, scal, ints;
+    CHK(part.alloc(ctx, sizeof(double) * (size_t)hw * ncol * 3));
+    double* pq = part.as<double>();
+    double* pr = pq + (size_t)hw * ncol;
+    double* pp = pr + (size_t)hw * ncol;
+    const size_t ns = (size_t)ncol * nshift;
+    CHK(scal.alloc(ctx, sizeof(double) * (8 * (size_t)ncol + 5 * ns)));
+    CHK(ints.alloc(ctx, sizeof(int) * (2 * (size_t)ncol + 2 * ns)));
+    MsState S{};
+    {
+        double* d = scal.as<double>();
+        S.rho = d; S.alpha = d + ncol; S.alpha_prev = d + 2 * ncol; S.beta = d + 3 * ncol;
+        S.beta_prev = d + 4 * ncol; S.stop2 = d + 5 * ncol;
+        double* e = d + 8 * (size_t)ncol;
+        S.zeta = e; S.zeta_prev = e + ns; S.zeta_new = e + 2 * ns; S.ak = e + 3 * ns; S.bk = e + 4 * ns;
+        int* i = ints.as<int>();
+        S.status = i; S.iters = i + ncol; S.act = i + 2 * ncol; S.kiters = i + 2 * ncol + ns;
+        S.nshift = nshift;
+        S.base = base;
+        for (int k = 0; k < nshift; k++) S.shift[k] = shifts[k] - sb;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    const FieldArg bo = parity_vec(b, 1).all();
+    SolveAcct acct;
+    HIPCHK(launch_convert(PREC_F64, bo, PREC_F64, f.r, n, ncol, nullptr, 0, st));
+    HIPCHK(launch_convert(PREC_F64, bo, PREC_F64, f.p, n, ncol, nullptr, 0, st));
+    for (int k = 0; k < nshift; k++) {
+        HIPCHK(launch_zero(PREC_F64, f.x[k], n, ncol, nullptr, 0, st));
+        if (k != base) HIPCHK(launch_convert(PREC_F64, bo, PREC_F64, f.pk[k], n, ncol, nullptr, 0, st));
+    }
+    HIPCHK(launch_norm2(PREC_F64, f.p, n, ncol, pp, hw, st));
+    HIPCHK(launch_fin_sum(pp, hw, ncol, S.rho, st));
+    HIPCHK(launch_ms_init(S, ncol, prm.tol * prm.tol, st));
+    std::vector<double> b2(ncol);
+    HIPCHK(hipMemcpyAsync(b2.data(), S.rho, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+
+    const int kchunk = prm.chunk > 0 ? prm.chunk : 8;
+    const long maxiter = prm.maxiter > 0 ? prm.maxiter : 100000;
+    OpCall c{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, S.status, 1 << COL_ACTIVE, st};
+    std::vector<int> hs(ncol);
+    long done_iters = 0;
+    while (true) {
+        for (int it = 0; it < kchunk; it++) {
+            CHK(k1(c, 0, f.p, t.all()));
+            CHK(tv(c, 0, 1, t.all(), f.p, q.all(), -kap * kap, pq, hw, hw));
+            HIPCHK(launch_fin_ms_alpha(S, pq, pp, hw, ncol, sb, st));
+            CHK(k1(c, 1, q.all(), t.all()));
+            CHK(tv(c, 1, 1, t.all(), q.all(), f.w, -kap * kap, nullptr, hw, hw));
+            HIPCHK(launch_ms_update1(S, f, sb, n, ncol, pr, hw, st));
+            HIPCHK(launch_fin_ms_beta(S, pr, hw, ncol, st));
+            HIPCHK(launch_ms_update2(S, f, n, ncol, pp, hw, st));
+        }
+        done_iters += kchunk;
+        acct.chunks++;
+        acct.iterations += kchunk;
+        acct.launches += 8L * kchunk;
+        HIPCHK(hipMemcpyAsync(hs.data(), S.status, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all = true;
+        for (int cc = 0; cc < ncol; cc++)
+            if (hs[cc] == COL_ACTIVE) all = false;
+        if (all || done_iters >= maxiter) break;
+    }
+    std::vector<int> kit(ns), act(ns), cit(ncol);
+    HIPCHK(hipMemcpyAsync(kit.data(), S.kiters, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(act.data(), S.act, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cit.data(), S.iters, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+    // true residuals |b - (Mhat^dag Mhat + sigma_k) x_k| in FP64
+    std::vector<double> r2(ns);
+    OpCall c64{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, nullptr, 1, st};
+    Vec bv = parity_vec(b, 1);
+    for (int k = 0; k < nshift; k++) {
+        Vec xk = parity_vec(x[k], 1);
+        CHK(op_fwd(c64, 0, xk, q, t, nullptr, hw));
+        CHK(op_dag_r(c64, 0, q, t, bv, w, nullptr, nullptr, hw));
+        HIPCHK(launch_axpy_norm(xk.all(), f.w, -shifts[k], n, ncol, pr, hw, st));
+        HIPCHK(launch_fin_sum(pr, hw, ncol, S.rho, st));
+        HIPCHK(hipMemcpyAsync(r2.data() + (size_t)k * ncol, S.rho, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // bytes: per iteration the four stencil launches, per active column their spinors and the base
+    // vectors, per active shift its x (rw) and direction (r, and rw unless it is the base)
+    {
+        const double Vh = g.Vh, s64 = sp_bytes(PREC_F64);
+        long long colit = 0, shit = 0, shit_nb = 0;
+        for (int cc = 0; cc < ncol; cc++) colit += cit[cc];
+        for (int cc = 0; cc < ncol; cc++)
+            for (int k = 0; k < nshift; k++) {
+                shit += kit[(size_t)cc * nshift + k];
+                if (k != base) shit_nb += kit[(size_t)cc * nshift + k];
+            }
+        int lock = 0;
+        for (int cc = 0; cc < ncol; cc++) lock = std::max(lock, cit[cc]);
+        acct.bytes += lock * iter_shared_bytes(op, PREC_F64);
+        acct.bytes += colit * Vh * s64 * (9 + 4 + 1 + 3);   // stencils, update1 base, update2 base
+        acct.bytes += shit * Vh * s64 * 3 + shit_nb * Vh * s64 * 2;
+        acct.bytes += nshift * (iter_shared_bytes(op, PREC_F64) + ncol * Vh * s64 * 13);  // true residuals
+    }
+    op->last.bytes = acct.bytes;
+    op->last.seconds = ms * 1e-3;
+    op->last.launches = acct.launches + 8L * nshift;
+    op->last.chunks = acct.chunks;
+    op->last.iterations = acct.iterations;
+    int rc = BQ_OK;
+    for (int k = 0; k < nshift; k++)
+        for (int cc = 0; cc < ncol; cc++) {
+            const size_t i = (size_t)cc * nshift + k;
+            const double tr = b2[cc] > 0 ? std::sqrt(r2[(size_t)k * ncol + cc] / b2[cc]) : 0.0;
+            int cst = BQ_OK;
+            if (!std::isfinite(tr) || hs[cc] == COL_FAILED) cst = std::isfinite(tr) ? BQ_ERR_NOT_CONVERGED : BQ_ERR_NONFINITE;
+            else if (act[i]) cst = BQ_ERR_NOT_CONVERGED;
+            if (info) {
+                bq_solve_info& in = info[(size_t)k * ncol + cc];
+                in.iters = kit[i];
+                in.reliable_updates = 0;
+                in.true_rel_resid = tr;
+                in.full_rel_resid = tr;
+                in.converged = cst == BQ_OK;
+                in.status = cst;
+            }
+            if (cst == BQ_ERR_NONFINITE) rc = cst;
+            else if (cst != BQ_OK && rc == BQ_OK) rc = cst;
+        }
+    if (rc == BQ_ERR_NOT_CONVERGED) return fail(rc, "some shift did not converge within maxiter");
+    if (rc == BQ_ERR_NONFINITE) return fail(rc, "non-finite value in the source or during the solve");
+    return BQ_OK;
 }
 
 int bq_solve_stats_get(bq_op op, bq_solve_stats* out)
@@ -1468,7 +2028,7 @@ int bq_trace(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_para
     if (nnoise < 1 || block < 1) return fail(BQ_ERR_INVALID, "nnoise and block must be >= 1");
     bq_solve_params p = *params;
     p.system = BQ_SYS_M;
-    if (!(p.tol > 0)) return fail(BQ_ERR_INVALID, "tol must be > 0");
+    CHK(check_solve_params(p));
     bq_context ctx = op->gauge->ctx;
     HIPCHK(hipSetDevice(ctx->device));
     const int* d = op->gauge->dims;
@@ -1476,7 +2036,7 @@ int bq_trace(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_para
     bq_field fa = nullptr, fb = nullptr;
     int rc = bq_field_create(ctx, d, BQ_FULL, BQ_F64, std::min(block, nnoise), &fa);
     if (rc == BQ_OK) rc = bq_field_create(ctx, d, BQ_FULL, BQ_F64, std::min(block, nnoise), &fb);
-    std::unique_ptr<bq_field_s> ua(fa), ub(fb);
+    FieldPtr ua(fa), ub(fb);
     if (rc != BQ_OK) return rc;
     hipStream_t st = ctx->stream;
     DevBuf part, sums;
@@ -1534,6 +2094,122 @@ int bq_trace(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_para
     return BQ_OK;
 }
 
+// Per noise eta (complex Z2, as bq_trace) and x1 = M^-1 eta, x2 = M^-1 x1, the terms whose noise
+// averages are the traces of the Measurements section and the abstract's reweighting traces:
+//   eta^dag x1, eta^dag x2, eta^dag gamma_5 x1, |x1|^2,
+//   eta^dag (dM/dkappa) x1 = eta^dag (c_SW S x1 - D x1),  eta^dag (dM/dc_SW) x1 = kappa eta^dag S x1,
+//   eta^dag (dM/dmu) x1 = -kappa eta^dag (dD/dmu) x1,
+// with S = (T - 1)/(kappa c_SW) the gauge field's clover term without its coefficient and dD/dmu
+// the time hops with e^{+mu} (forward) and -e^{-mu} (backward).
+int bq_trace_estimators(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_params* params, double* est,
+                        bq_solve_info* info)
+{
+    if (!op || !params || !est) return fail(BQ_ERR_INVALID, "NULL argument");
+    if (nnoise < 1 || block < 1) return fail(BQ_ERR_INVALID, "nnoise and block must be >= 1");
+    bq_solve_params p = *params;
+    p.system = BQ_SYS_M;
+    CHK(check_solve_params(p));
+    bq_context ctx = op->gauge->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    const int* d = op->gauge->dims;
+    const Geom& g = op->gauge->g;
+    const int nbmax = std::min(block, nnoise);
+    bq_field fa = nullptr, fb = nullptr, fc = nullptr;
+    int rc = bq_field_create(ctx, d, BQ_FULL, BQ_F64, nbmax, &fa);
+    if (rc == BQ_OK) rc = bq_field_create(ctx, d, BQ_FULL, BQ_F64, nbmax, &fb);
+    if (rc == BQ_OK) rc = bq_field_create(ctx, d, BQ_FULL, BQ_F64, nbmax, &fc);
+    FieldPtr ua(fa), ub(fb), uc(fc);
+    if (rc != BQ_OK) return rc;
+    hipStream_t st = ctx->stream;
+    DevBuf part, sums;
+    const int nw = (int)(2 * fa->half_sites / kTile);
+    CHK(part.alloc(ctx, sizeof(double) * 2 * nbmax * nw));
+    CHK(sums.alloc(ctx, sizeof(double) * 2 * nbmax * BQ_TR_COUNT));
+    double* dsum = sums.as<double>();
+    int worst = BQ_OK;
+    SolveAcct acct;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    const double kap = op->kappa, csw = op->csw, mu = op->mu;
+    const double s64 = sp_bytes(PREC_F64);
+    for (int n0 = 0; n0 < nnoise; n0 += block) {
+        const int nb = std::min(block, nnoise - n0);
+        OpCall c64{op, PREC_F64, get_tune(ctx, PREC_F64, nb), nb, nullptr, 1, st};
+        Vec a[2] = {parity_vec(fa, 0), parity_vec(fa, 1)}, b[2] = {parity_vec(fb, 0), parity_vec(fb, 1)},
+            cc[2] = {parity_vec(fc, 0), parity_vec(fc, 1)};
+        Vec va = field_vec(fa, 0, 2), vb = field_vec(fb, 0, 2), vc = field_vec(fc, 0, 2);
+        const int n = va.sites();
+        // <x, y> (or <x, gamma_5 y>) of the block's columns into dsum[term][col][re, im]
+        auto dot = [&](const Vec& x, const Vec& y, int term, int g5) -> int {
+            HIPCHK(launch_dot(PREC_F64, x.all(), y.all(), n, nb, part.as<double>(), nw, st, g5));
+            HIPCHK(launch_fin_sum(part.as<double>(), nw, 2 * nb, dsum + (size_t)term * 2 * nbmax, st));
+            acct.bytes += 2.0 * nb * n * s64;
+            acct.launches += 2;
+            return BQ_OK;
+        };
+        for (int par = 0; par < 2; par++) HIPCHK(launch_z2_noise(seed, n0, g, par, a[par].all(), nb, st));
+        acct.bytes += (double)nb * n * s64;
+        // x1 = M^-1 eta
+        int r1 = solve_views(op, a[0], a[1], b[0], b[1], nb, p, info ? info + n0 : nullptr, st, acct);
+        if (r1 != BQ_OK && r1 != BQ_ERR_NOT_CONVERGED) return r1;
+        if (r1 != BQ_OK) worst = r1;
+        CHK(dot(va, vb, BQ_TR_MINV, 0));
+        CHK(dot(va, vb, BQ_TR_G5_MINV, 1));
+        CHK(dot(vb, vb, BQ_TR_MDAGM_INV, 0));
+        // S x1; the c_SW derivative is kappa <eta, S x1>
+        for (int par = 0; par < 2; par++)
+            HIPCHK(launch_clover_apply(PREC_F64, g, op->gauge->B[par].p, b[par].all(), cc[par].all(), nb, st));
+        CHK(dot(va, vc, BQ_TR_DM_DCSW, 0));
+        // (dM/dkappa) x1 = c_SW S x1 - D x1, in place
+        for (int par = 0; par < 2; par++)
+            CHK(hopv(c64, 0, par, b[1 - par].all(), cc[par].all(), cc[par].all(), csw, -1.0));
+        CHK(dot(va, vc, BQ_TR_DM_DKAPPA, 0));
+        // (dD/dmu) x1 = D'(forward e^{+mu}, backward -e^{-mu}) x1 - D'(no time hops) x1; the mu
+        // derivative is -kappa <eta, (dD/dmu) x1>
+        for (int par = 0; par < 2; par++) CHK(hop_coef(c64, par, b[1 - par].all(), cc[par].all(), FieldArg(), 0.0, 1.0, 0.0, 0.0));
+        for (int par = 0; par < 2; par++)
+            CHK(hop_coef(c64, par, b[1 - par].all(), cc[par].all(), cc[par].all(), -1.0, 1.0, std::exp(mu), -std::exp(-mu)));
+        CHK(dot(va, vc, BQ_TR_DM_DMU, 0));
+        {
+            const double sh = stencil_shared(op, PREC_F64), C64 = (double)g.Vh * 72 * 8.0;
+            acct.bytes += 2 * C64 + nb * n * 2.0 * s64;                    // S x1
+            acct.bytes += 2 * (sh - C64) + nb * n * 3.0 * s64;            // c_SW S x1 - D x1
+            acct.bytes += 4 * (sh - C64) + nb * n * 5.0 * s64;            // dD/dmu x1
+            acct.launches += 6;
+        }
+        // x2 = M^-1 x1
+        int r2 = solve_views(op, b[0], b[1], cc[0], cc[1], nb, p, info ? info + nnoise + n0 : nullptr, st, acct);
+        if (r2 != BQ_OK && r2 != BQ_ERR_NOT_CONVERGED) return r2;
+        if (r2 != BQ_OK) worst = r2;
+        CHK(dot(va, vc, BQ_TR_MINV2, 0));
+        std::vector<double> h((size_t)2 * nbmax * BQ_TR_COUNT);
+        HIPCHK(hipMemcpyAsync(h.data(), dsum, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const double scale[BQ_TR_COUNT] = {1, 1, 1, 1, 1, kap, -kap};
+        for (int c = 0; c < nb; c++)
+            for (int t = 0; t < BQ_TR_COUNT; t++) {
+                const double* v = h.data() + ((size_t)t * nbmax + c) * 2;
+                est[((size_t)(n0 + c) * BQ_TR_COUNT + t) * 2 + 0] = scale[t] * v[0];
+                est[((size_t)(n0 + c) * BQ_TR_COUNT + t) * 2 + 1] = scale[t] * v[1];
+            }
+    }
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    op->last.bytes = acct.bytes;
+    op->last.seconds = ms * 1e-3;
+    op->last.launches = acct.launches;
+    op->last.chunks = acct.chunks;
+    op->last.iterations = acct.iterations;
+    if (worst != BQ_OK) return fail(worst, "some trace solve did not converge");
+    return BQ_OK;
+}
+
 int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march)
 {
     if (!ctx || !recon || !R || !bs || !march) return fail(BQ_ERR_INVALID, "NULL argument");
@@ -1565,9 +2241,9 @@ int bq_autotune(bq_op op, int prec, int nrhs)
     HIPCHK(hipSetDevice(ctx->device));
     bq_field fi = nullptr, fo = nullptr;
     CHK(bq_field_create(ctx, op->gauge->dims, BQ_ODD, prec, nrhs, &fi));
-    std::unique_ptr<bq_field_s> ui(fi);
+    FieldPtr ui(fi);
     CHK(bq_field_create(ctx, op->gauge->dims, BQ_EVEN, prec, nrhs, &fo));
-    std::unique_ptr<bq_field_s> uo(fo);
+    FieldPtr uo(fo);
     const int rprec = prec == PREC_F64 ? PREC_F64 : PREC_F32;
     const auto had = ctx->tune.find({prec, nrhs});
     const bool had_entry = had != ctx->tune.end();
@@ -1590,6 +2266,7 @@ int bq_autotune(bq_op op, int prec, int nrhs)
             for (int R = 1; R <= std::min(nrhs, 4); R++)
                 for (int bs : {64, 128, 256, 512}) {
                     if (!hop_variant_exists(prec, rprec, recon, R, EPI_TINV)) continue;
+                    if (recon == 12 && !op->gauge->get(prec, 12)) continue;  // not an SU(3) field
                     const Tune t{recon, R, bs, march};
                     const double ms = time_of(t, 5);
                     if (ms < 1e300) cand.push_back({ms, t});
@@ -1656,6 +2333,7 @@ struct Request {
     std::vector<int> slots;
     int state = REQ_QUEUED;
     int rc = BQ_OK;
+    int waited = 0;  // steps spent blocked at the head of its session's queue
     std::vector<bq_solve_info> info;
 };
 
@@ -1675,14 +2353,17 @@ struct Session {
     int used = 0;
     ~Session()
     {
+        if (st) (void)hipStreamSynchronize(st);
         if (hflags) (void)hipHostFree(hflags);
         if (st) (void)hipStreamDestroy(st);
+        if (g) g->nsess--;
     }
 };
 
 struct bq_server_s {
     bq_context ctx = nullptr;
     int cap = 16, chunk = 16;
+    int backfill = 8;  // steps a blocked request may be passed by narrower ones of its session
     std::vector<std::unique_ptr<Session>> sessions;
     std::vector<Request*> queue;  // FIFO
     std::map<uint64_t, std::unique_ptr<Request>> reqs;
@@ -1706,6 +2387,7 @@ static int session_get(bq_server S, bq_gauge g, double mu, int prec, Session** o
         }
     auto s = std::make_unique<Session>();
     s->g = g;
+    g->nsess++;  // released by the session's destructor
     s->mu = mu;
     s->prec = prec;
     s->cap = S->cap;
@@ -1825,9 +2507,18 @@ static int retire(bq_server S, Session* s, std::vector<Request*>& done)
     OpCall c64{&s->stub, PREC_F64, get_tune(s->g->ctx, PREC_F64, cap), cap, w->cs.status, m, st};
     c64.ct = &s->ct;
     CHK(k1(c64, 0, s->xfull.half(1), s->xfull.half(0), s->bfull.half(0), 1.0, 0.0, FK_KAPPA));
-    std::vector<double> h(2 * cap);
+    // |b - M x|^2 on the full lattice (t64 and q64 as even / odd scratch) and |b|^2
+    const int hw = w->hw;
+    CHK(tvr(c64, 0, 0, s->xfull.half(1), s->xfull.half(0), s->bfull.half(0), w->t64.all(), 0.0, nullptr, w->partial, hw,
+            2 * hw, FK_MKAPPA));
+    CHK(tvr(c64, 0, 1, s->xfull.half(0), s->xfull.half(1), s->bfull.half(1), w->q64.all(), 0.0, nullptr,
+            w->partial + hw, hw, 2 * hw, FK_MKAPPA));
+    HIPCHK(launch_fin_sum(w->partial, 2 * hw, cap, w->dtmp + 2 * cap, st));
+    HIPCHK(launch_norm2(PREC_F64, s->bfull.all(), s->bfull.sites(), cap, w->partial, 2 * hw, st));
+    HIPCHK(launch_fin_sum(w->partial, 2 * hw, cap, w->dtmp + 3 * cap, st));
+    std::vector<double> h(4 * cap);
     std::vector<int> hi(4 * cap);
-    HIPCHK(hipMemcpyAsync(h.data(), w->dtmp, sizeof(double) * 2 * cap, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h.data(), w->dtmp, sizeof(double) * 4 * cap, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hi.data(), w->cs.status, sizeof(int) * 4 * cap, hipMemcpyDeviceToHost, st));
     const Geom& g = s->g->g;
     const size_t V = 2 * (size_t)g.Vh;
@@ -1852,7 +2543,7 @@ static int retire(bq_server S, Session* s, std::vector<Request*>& done)
             in.iters = hi[cap + c];
             in.reliable_updates = hi[3 * cap + c];
             in.true_rel_resid = tr;
-            in.full_rel_resid = tr;
+            in.full_rel_resid = h[3 * cap + c] > 0 ? std::sqrt(h[2 * cap + c] / h[3 * cap + c]) : 0.0;
             in.converged = std::isfinite(tr) && tr <= q->tol;
             in.status = !std::isfinite(tr) ? BQ_ERR_NONFINITE : (in.converged ? BQ_OK : BQ_ERR_NOT_CONVERGED);
             if (in.status != BQ_OK && q->rc == BQ_OK) q->rc = in.status;
@@ -1880,6 +2571,7 @@ int bq_server_create(bq_context ctx, int slots, int chunk, bq_server* out)
     S->cap = slots;
     S->chunk = chunk > 0 ? chunk : 16;
     *out = S.release();
+    ctx->nhandles++;
     return BQ_OK;
 }
 
@@ -1889,8 +2581,13 @@ int bq_server_submit(bq_server S, bq_gauge g, double kappa, double csw, double m
     if (!S || !g || !b || !x || !ticket) return fail(BQ_ERR_INVALID, "NULL argument");
     if (g->ctx != S->ctx) return fail(BQ_ERR_INVALID, "gauge field of another context");
     if (nrhs < 1 || nrhs > S->cap) return fail(BQ_ERR_INVALID, "nrhs must be in 1..%d", S->cap);
-    if (!(tol > 0)) return fail(BQ_ERR_INVALID, "tol must be > 0");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(BQ_ERR_INVALID, "tol must be > 0");
     if (inner_prec < BQ_F64 || inner_prec > BQ_F16) return fail(BQ_ERR_INVALID, "bad inner precision");
+    if (!std::isfinite(kappa) || !std::isfinite(csw) || !std::isfinite(mu))
+        return fail(BQ_ERR_INVALID, "kappa, c_SW and mu must be finite");
+    if (!g->get(PREC_F64, 12) || !g->get(inner_prec, 12))
+        return fail(BQ_ERR_UNSUPPORTED, "the server needs two-row links: this gauge field is not SU(3) "
+                                        "(max deviation %.3g)", g->su3_dev);
     auto q = std::make_unique<Request>();
     q->ticket = S->next++;
     q->g = g;
@@ -1909,16 +2606,48 @@ int bq_server_submit(bq_server S, bq_gauge g, double kappa, double csw, double m
     return BQ_OK;
 }
 
+// A request that cannot be admitted for a reason other than memory (its clover is not positive
+// definite, a device call failed) is finished at once with that status; the others go on.
+static void finish_failed(Request* q, int rc)
+{
+    q->state = REQ_DONE;
+    q->rc = rc;
+    bq_solve_info bad{};
+    bad.status = rc;
+    q->info.assign(q->nrhs, bad);
+}
+
+// undo a partial admission: free the request's slots and operator, back to the queue
+static void unadmit(Request* q, Session* s)
+{
+    for (int c : q->slots) {
+        s->slot[c] = nullptr;
+        s->hflags[c] = 0;
+        for (int pr = 0; pr < 3; pr++) s->ct.T[pr][0][c] = s->ct.T[pr][1][c] = s->ct.Tinv[pr][0][c] = nullptr;
+    }
+    if (q->op) bq_op_free(q->op);
+    q->op = nullptr;
+    q->slots.clear();
+    q->sess = nullptr;
+    q->state = REQ_QUEUED;
+}
+
 int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone)
 {
     if (!S || !ndone) return fail(BQ_ERR_INVALID, "NULL argument");
     *ndone = 0;
     bq_context ctx = S->ctx;
     HIPCHK(hipSetDevice(ctx->device));
-    // 1. admission, FIFO per session (a request that does not fit waits; others may pass it)
+    auto report = [&](Request* q) {
+        if (*ndone < max_done && done_tickets) done_tickets[*ndone] = q->ticket;
+        (*ndone)++;
+    };
+    // 1. admission in arrival order per session.  A request that does not fit waits at the head
+    //    of its session; later, narrower requests may pass it (backfill) until it has waited
+    //    S->backfill steps, after which the session admits nothing else until it fits.
     std::vector<Session*> fresh;
     std::vector<Request*> keep;
-    std::map<Session*, bool> blocked;
+    std::map<Session*, Request*> head;  // first blocked request per session this step
     for (Request* q : S->queue) {
         Session* s = nullptr;
         int rc = session_get(S, q->g, q->mu, q->prec, &s);
@@ -1926,9 +2655,16 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
             keep.push_back(q);
             continue;
         }
-        if (rc != BQ_OK) return rc;
-        if (blocked[s] || s->cap - s->used < q->nrhs) {
-            blocked[s] = true;
+        if (rc != BQ_OK) {
+            finish_failed(q, rc);
+            report(q);
+            continue;
+        }
+        Request*& h = head[s];
+        const bool fits = s->cap - s->used >= q->nrhs;
+        const bool may_pass = h == nullptr || h->waited < S->backfill;
+        if (!fits || !may_pass) {
+            if (h == nullptr) h = q;
             keep.push_back(q);
             continue;
         }
@@ -1938,22 +2674,26 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
         }
         rc = admit(S, q, s);
         if (rc == BQ_ERR_OOM) {  // no room for the operator now: undo and wait
-            for (int c : q->slots) {
-                s->slot[c] = nullptr;
-                s->hflags[c] = 0;
-            }
-            if (q->op) bq_op_free(q->op);
-            q->op = nullptr;
-            q->slots.clear();
-            q->state = REQ_QUEUED;
-            blocked[s] = true;
+            unadmit(q, s);
+            if (h == nullptr) h = q;
             keep.push_back(q);
             continue;
         }
-        if (rc != BQ_OK) return rc;
+        if (rc != BQ_OK) {
+            unadmit(q, s);
+            finish_failed(q, rc);
+            report(q);
+            continue;
+        }
     }
+    for (auto& kv : head)
+        if (kv.second) kv.second->waited++;
     S->queue = keep;
-    for (Session* s : fresh) CHK(prepare_new(s));
+    for (Session* s : fresh) {
+        bool any = false;
+        for (int c = 0; c < s->cap; c++) any |= s->hflags[c] != 0;
+        if (any) CHK(prepare_new(s));
+    }
     // 2. one chunk on every session with work, all launched before any wait
     std::vector<Session*> run;
     for (auto& s : S->sessions)
@@ -1982,9 +2722,7 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
         }
         if (!done.empty()) {
             CHK(retire(S, s, done));
-            for (Request* q : done)
-                if (*ndone < max_done && done_tickets) done_tickets[(*ndone)++] = q->ticket;
-                else (*ndone)++;
+            for (Request* q : done) report(q);
         }
     }
     return BQ_OK;
@@ -2015,14 +2753,36 @@ int bq_server_pending(bq_server S, int* queued, int* running)
     return BQ_OK;
 }
 
+int bq_server_set_backfill(bq_server S, int steps)
+{
+    if (!S || steps < 0) return fail(BQ_ERR_INVALID, "NULL server or negative step count");
+    S->backfill = steps;
+    return BQ_OK;
+}
+
+int bq_server_release(bq_server S, bq_gauge g)
+{
+    if (!S || !g) return fail(BQ_ERR_INVALID, "NULL argument");
+    for (auto& kv : S->reqs)
+        if (kv.second->g == g && kv.second->state != REQ_DONE)
+            return fail(BQ_ERR_BUSY, "request %llu on this gauge field is still queued or running",
+                        (unsigned long long)kv.first);
+    (void)hipSetDevice(S->ctx->device);
+    auto& v = S->sessions;
+    v.erase(std::remove_if(v.begin(), v.end(), [g](const std::unique_ptr<Session>& s) { return s->g == g; }), v.end());
+    return BQ_OK;
+}
+
 int bq_server_free(bq_server S)
 {
     if (!S) return BQ_OK;
     (void)hipSetDevice(S->ctx->device);
+    for (auto& s : S->sessions) (void)hipStreamSynchronize(s->st);
     for (auto& kv : S->reqs)
         if (kv.second->op) bq_op_free(kv.second->op);
-    for (auto& s : S->sessions) (void)hipStreamSynchronize(s->st);
+    bq_context ctx = S->ctx;
     delete S;
+    ctx_release_handle(ctx);
     return BQ_OK;
 }
 

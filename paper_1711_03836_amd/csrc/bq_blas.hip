@@ -131,7 +131,9 @@ __global__ void k_norm2(SpinorPtr<P> x, int n, double* partial, int nwaves)
     if ((threadIdx.x & 63) == 0 && w < nwaves) partial[(size_t)c * nwaves + w] = s;
 }
 
-// <x, y> = sum conj(x) y, FP64 fields; partials [col][re/im][wave]
+// <x, y> = sum conj(x) y (G5: <x, gamma_5 y>, gamma_5 = diag(1,1,-1,-1) in spin), FP64 fields;
+// partials [col][re/im][wave]
+template <bool G5>
 __global__ void k_dot(SpinorPtr<P64> x, SpinorPtr<P64> y, int n, double* partial, int nwaves)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,8 +145,9 @@ __global__ void k_dot(SpinorPtr<P64> x, SpinorPtr<P64> y, int n, double* partial
         load_spinor(y, c, j, b);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            re += a[k].re * b[k].re + a[k].im * b[k].im;
-            im += a[k].re * b[k].im - a[k].im * b[k].re;
+            const double sg = (G5 && k >= 6) ? -1.0 : 1.0;  // components 6..11 are spins 2 and 3
+            re += sg * (a[k].re * b[k].re + a[k].im * b[k].im);
+            im += sg * (a[k].re * b[k].im - a[k].im * b[k].re);
         }
     }
     re = wave_sum(re);
@@ -244,6 +247,47 @@ __global__ void k_restart(SpinorPtr<P64> r64, SpinorPtr<PRS> rs, SpinorPtr<PP> p
     store_spinor(p, c, j, pv);
 }
 
+// Distance of every link from SU(3): max over links of max(max_ab |(U U^dag - 1)_ab|, |det U - 1|),
+// one partial maximum per workgroup (the host takes the maximum of the partials).
+__global__ void k_link_su3_dev(const double2* __restrict__ canon, size_t nlinks, double* partial)
+{
+    __shared__ double w[4];
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double dev = 0.0;
+    if (k < nlinks) {
+        cx<double> u[9];
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            const double2 t = canon[k * 9 + e];
+            u[e] = {t.x, t.y};
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                cx<double> s = {0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 3; c++) s = cmacc(s, u[b * 3 + c], u[a * 3 + c]);  // sum_c U_ac conj(U_bc)
+                if (a == b) s.re -= 1.0;
+                dev = fmax(dev, fmax(fabs(s.re), fabs(s.im)));
+            }
+        const cx<double> m0 = csub(cmul(u[4], u[8]), cmul(u[5], u[7]));
+        const cx<double> m1 = csub(cmul(u[5], u[6]), cmul(u[3], u[8]));
+        const cx<double> m2 = csub(cmul(u[3], u[7]), cmul(u[4], u[6]));
+        cx<double> det = cmul(u[0], m0);
+        det = cmac(det, u[1], m1);
+        det = cmac(det, u[2], m2);
+        det.re -= 1.0;
+        dev = fmax(dev, sqrt(cnorm2(det)));
+        if (!isfinite(dev)) dev = INFINITY;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = dev;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(w[0], w[1]), fmax(w[2], w[3]));
+}
+
 // complex Z2 noise from SplitMix64 used as a counter-based generator:
 // output k of stream `seed` is mix(seed + (k+1) * 0x9E3779B97F4A7C15);
 // component (noise n, lexicographic site i, spin s, colour c) uses k = (n*V + i)*12 + 3s + c,
@@ -291,6 +335,7 @@ __device__ double block_sum(const double* __restrict__ part, int n)
     for (; i < n; i += 256) a[0] += part[i];
     double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = wave_sum(s);
+    __syncthreads();  // a previous call's readers of w are done before it is overwritten
     if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
     __syncthreads();
     return (w[0] + w[1]) + (w[2] + w[3]);
@@ -373,6 +418,8 @@ constexpr int kBS = 256;
 
 inline dim3 grid2(int n, int ncol) { return dim3((n + kBS - 1) / kBS, ncol); }
 
+inline bool prec_ok(int prec) { return prec == PREC_F64 || prec == PREC_F32 || prec == PREC_F16; }
+
 }  // namespace
 
 hipError_t launch_links_import(const double2* canon, const Geom& g, int parity, int prec, int recon, void* const dst[4],
@@ -423,6 +470,7 @@ hipError_t launch_convert(int sprec, FieldArg src, int dprec, FieldArg dst, int 
 {
     const dim3 grid = grid2(n, ncol);
 #define CV(PS, PD) hipLaunchKernelGGL((k_convert<PS, PD>), grid, dim3(kBS), 0, st, sp<PS>(src), sp<PD>(dst), n, status, statmask)
+    if (!prec_ok(sprec) || !prec_ok(dprec)) return hipErrorInvalidValue;
     const int key = sprec * 3 + dprec;
     switch (key) {
     case PREC_F64 * 3 + PREC_F64: CV(P64, P64); break;
@@ -464,10 +512,14 @@ hipError_t launch_zero(int prec, FieldArg x, int n, int ncol, const int* status,
     return hipGetLastError();
 }
 
-hipError_t launch_dot(int prec, FieldArg x, FieldArg y, int n, int ncol, double* partial, int nwaves, hipStream_t st)
+hipError_t launch_dot(int prec, FieldArg x, FieldArg y, int n, int ncol, double* partial, int nwaves, hipStream_t st,
+                      int gamma5)
 {
     if (prec != PREC_F64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dot, grid2(n, ncol), dim3(kBS), 0, st, sp<P64>(x), sp<P64>(y), n, partial, nwaves);
+    if (gamma5)
+        hipLaunchKernelGGL(k_dot<true>, grid2(n, ncol), dim3(kBS), 0, st, sp<P64>(x), sp<P64>(y), n, partial, nwaves);
+    else
+        hipLaunchKernelGGL(k_dot<false>, grid2(n, ncol), dim3(kBS), 0, st, sp<P64>(x), sp<P64>(y), n, partial, nwaves);
     return hipGetLastError();
 }
 
@@ -513,6 +565,15 @@ hipError_t launch_restart(FieldArg r64, int rsprec, FieldArg rs, int pprec, Fiel
     return hipGetLastError();
 }
 
+int link_su3_parts(size_t nlinks) { return (int)((nlinks + kBS - 1) / kBS); }
+
+hipError_t launch_link_su3_dev(const double2* canon, size_t nlinks, double* partial, hipStream_t st)
+{
+    if (nlinks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_link_su3_dev, dim3(link_su3_parts(nlinks)), dim3(kBS), 0, st, canon, nlinks, partial);
+    return hipGetLastError();
+}
+
 hipError_t launch_z2_noise(uint64_t seed, long n0, const Geom& g, int parity, FieldArg dst, int ncol, hipStream_t st)
 {
     hipLaunchKernelGGL(k_z2_noise, grid2(g.Vh, ncol), dim3(kBS), 0, st, seed, n0, g, parity, sp<P64>(dst));
@@ -540,6 +601,244 @@ hipError_t launch_fin_reliable(const CgScalars& s, const double* partial, int nw
 hipError_t launch_fin_sum(const double* partial, int nwaves, int ncol, double* out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fin_sum, dim3(ncol), dim3(256), 0, st, partial, nwaves, out);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// multishift CG
+// --------------------------------------------------------------------------
+
+namespace {
+
+__global__ void k_axpy_norm(SpinorPtr<P64> x, SpinorPtr<P64> y, double a, int n, double* partial, int nwaves)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    double s = 0.0;
+    if (j < n) {
+        cx<double> xv[12], yv[12];
+        load_spinor(x, c, j, xv);
+        load_spinor(y, c, j, yv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            yv[k].re = fmadd(a, xv[k].re, yv[k].re);
+            yv[k].im = fmadd(a, xv[k].im, yv[k].im);
+            s += yv[k].re * yv[k].re + yv[k].im * yv[k].im;
+        }
+        store_spinor(y, c, j, yv);
+    }
+    s = wave_sum(s);
+    const int w = j >> kTileLog;
+    if ((threadIdx.x & 63) == 0 && w < nwaves) partial[(size_t)c * nwaves + w] = s;
+}
+
+__global__ void k_ms_init(const MsState s, int ncol, double tol2)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    const double r2 = s.rho[c];
+    s.stop2[c] = tol2 * r2;
+    s.alpha_prev[c] = 1.0;
+    s.beta_prev[c] = 0.0;
+    s.iters[c] = 0;
+    const int st = !isfinite(r2) ? COL_FAILED : (r2 > 0.0 ? COL_ACTIVE : COL_DONE);
+    s.status[c] = st;
+    for (int k = 0; k < s.nshift; k++) {
+        const int i = c * s.nshift + k;
+        s.zeta[i] = s.zeta_prev[i] = s.zeta_new[i] = 1.0;
+        s.ak[i] = s.bk[i] = 0.0;
+        s.act[i] = st == COL_ACTIVE;
+        s.kiters[i] = 0;
+    }
+}
+
+// alpha of the base system and, per active shift, zeta_{j+1} and the shift's alpha
+__global__ void k_fin_ms_alpha(const MsState s, const double* pq, const double* pp, int nwaves, double sigma_b)
+{
+    const int c = blockIdx.x;
+    if (s.status[c] != COL_ACTIVE) return;  // uniform per block
+    const double qq = block_sum(pq + (size_t)c * nwaves, nwaves);
+    const double ppn = sigma_b != 0.0 ? block_sum(pp + (size_t)c * nwaves, nwaves) : 0.0;
+    if (threadIdx.x != 0) return;
+    const double pAp = qq + sigma_b * ppn;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+        s.status[c] = COL_FAILED;
+        return;
+    }
+    const double al = s.rho[c] / pAp, ap = s.alpha_prev[c], bp = s.beta_prev[c];
+    s.alpha[c] = al;
+    for (int k = 0; k < s.nshift; k++) {
+        const int i = c * s.nshift + k;
+        if (!s.act[i]) continue;
+        const double z = s.zeta[i], zp = s.zeta_prev[i];
+        const double zn = z * zp * ap / (al * bp * (zp - z) + zp * ap * (1.0 + s.shift[k] * al));
+        s.zeta_new[i] = zn;
+        s.ak[i] = al * zn / z;
+    }
+}
+
+// beta of the base system; per shift: beta, convergence (|zeta_{j+1}| |r_{j+1}| <= tol |b|), rotation
+__global__ void k_fin_ms_beta(const MsState s, const double* pr, int nwaves)
+{
+    const int c = blockIdx.x;
+    if (s.status[c] != COL_ACTIVE) return;
+    const double rho = block_sum(pr + (size_t)c * nwaves, nwaves);
+    if (threadIdx.x != 0) return;
+    s.iters[c] += 1;
+    if (!isfinite(rho)) {
+        s.status[c] = COL_FAILED;
+        return;
+    }
+    const double be = rho / s.rho[c];
+    int any = 0;
+    for (int k = 0; k < s.nshift; k++) {
+        const int i = c * s.nshift + k;
+        if (!s.act[i]) continue;
+        const double z = s.zeta[i], zn = s.zeta_new[i];
+        const double q = zn / z;
+        s.bk[i] = be * q * q;
+        s.kiters[i] += 1;
+        if (zn * zn * rho <= s.stop2[c] || !isfinite(zn)) {
+            s.act[i] = 0;
+        } else {
+            s.zeta_prev[i] = z;
+            s.zeta[i] = zn;
+            any = 1;
+        }
+    }
+    s.alpha_prev[c] = s.alpha[c];
+    s.beta_prev[c] = be;
+    s.beta[c] = be;
+    s.rho[c] = rho;
+    if (!any) s.status[c] = COL_DONE;
+}
+
+__global__ void k_ms_update1(const MsState s, const MsFields f, double sigma_b, int n, double* partial, int nwaves)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    const bool on = s.status[c] == COL_ACTIVE;  // uniform per block
+    double nr = 0.0;
+    if (on && j < n) {
+        const SpinorPtr<P64> r = sp<P64>(f.r), w = sp<P64>(f.w), p = sp<P64>(f.p);
+        const double al = s.alpha[c];
+        cx<double> rv[12], wv[12], pv[12];
+        load_spinor(r, c, j, rv);
+        load_spinor(w, c, j, wv);
+        load_spinor(p, c, j, pv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            rv[k].re = fmadd(-al, fmadd(sigma_b, pv[k].re, wv[k].re), rv[k].re);
+            rv[k].im = fmadd(-al, fmadd(sigma_b, pv[k].im, wv[k].im), rv[k].im);
+            nr += rv[k].re * rv[k].re + rv[k].im * rv[k].im;
+        }
+        store_spinor(r, c, j, rv);
+        for (int q = 0; q < s.nshift; q++) {
+            const int i = c * s.nshift + q;
+            if (!s.act[i]) continue;
+            const double a = s.ak[i];
+            cx<double> xv[12], pk[12];
+            const SpinorPtr<P64> X = sp<P64>(f.x[q]);
+            load_spinor(X, c, j, xv);
+            if (q == s.base) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) pk[k] = pv[k];
+            } else {
+                load_spinor(sp<P64>(f.pk[q]), c, j, pk);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                xv[k].re = fmadd(a, pk[k].re, xv[k].re);
+                xv[k].im = fmadd(a, pk[k].im, xv[k].im);
+            }
+            store_spinor(X, c, j, xv);
+        }
+    }
+    nr = wave_sum(nr);
+    const int w = j >> kTileLog;
+    if (on && (threadIdx.x & 63) == 0 && w < nwaves) partial[(size_t)c * nwaves + w] = nr;
+}
+
+__global__ void k_ms_update2(const MsState s, const MsFields f, int n, double* partial, int nwaves)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    const bool on = s.status[c] == COL_ACTIVE;
+    double np = 0.0;
+    if (on && j < n) {
+        const SpinorPtr<P64> r = sp<P64>(f.r), p = sp<P64>(f.p);
+        cx<double> rv[12], pv[12];
+        load_spinor(r, c, j, rv);
+        for (int q = 0; q < s.nshift; q++) {
+            const int i = c * s.nshift + q;
+            if (q == s.base || !s.act[i]) continue;
+            const double z = s.zeta[i], b = s.bk[i];
+            const SpinorPtr<P64> P = sp<P64>(f.pk[q]);
+            cx<double> pk[12];
+            load_spinor(P, c, j, pk);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                pk[k].re = fmadd(b, pk[k].re, z * rv[k].re);
+                pk[k].im = fmadd(b, pk[k].im, z * rv[k].im);
+            }
+            store_spinor(P, c, j, pk);
+        }
+        load_spinor(p, c, j, pv);
+        const double be = s.beta[c];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            pv[k].re = fmadd(be, pv[k].re, rv[k].re);
+            pv[k].im = fmadd(be, pv[k].im, rv[k].im);
+            np += pv[k].re * pv[k].re + pv[k].im * pv[k].im;
+        }
+        store_spinor(p, c, j, pv);
+    }
+    np = wave_sum(np);
+    const int w = j >> kTileLog;
+    if (on && (threadIdx.x & 63) == 0 && w < nwaves) partial[(size_t)c * nwaves + w] = np;
+}
+
+}  // namespace
+
+hipError_t launch_axpy_norm(FieldArg x, FieldArg y, double a, int n, int ncol, double* partial, int nwaves,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpy_norm, grid2(n, ncol), dim3(kBS), 0, st, sp<P64>(x), sp<P64>(y), a, n, partial, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_init(const MsState& s, int ncol, double tol2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ms_init, dim3((ncol + 63) / 64), dim3(64), 0, st, s, ncol, tol2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_ms_alpha(const MsState& s, const double* pq, const double* pp, int nwaves, int ncol,
+                               double sigma_b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fin_ms_alpha, dim3(ncol), dim3(256), 0, st, s, pq, pp, nwaves, sigma_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_ms_beta(const MsState& s, const double* pr, int nwaves, int ncol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fin_ms_beta, dim3(ncol), dim3(256), 0, st, s, pr, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_update1(const MsState& s, const MsFields& f, double sigma_b, int n, int ncol, double* partial,
+                             int nwaves, hipStream_t st)
+{
+    if (s.nshift < 1 || s.nshift > kMaxShifts) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ms_update1, grid2(n, ncol), dim3(kBS), 0, st, s, f, sigma_b, n, partial, nwaves);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_update2(const MsState& s, const MsFields& f, int n, int ncol, double* partial, int nwaves,
+                             hipStream_t st)
+{
+    if (s.nshift < 1 || s.nshift > kMaxShifts) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ms_update2, grid2(n, ncol), dim3(kBS), 0, st, s, f, n, partial, nwaves);
     return hipGetLastError();
 }
 

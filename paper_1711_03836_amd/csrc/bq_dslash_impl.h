@@ -1,6 +1,6 @@
 // The hopping-term stencil (Eq. 1) with fused clover epilogues (Eq. 2).
-// Internal header: each bq_dslash_<prec>.hip instantiates it for one storage
-// precision.
+// Internal header: bq_dslash_inst.hip instantiates it for one storage precision
+// and one number of columns per thread per compilation.
 //
 // One thread owns one output site of one checkerboard and R right-hand sides.
 // For each of the 8 hops it loads the link once, and for each of its columns
@@ -947,22 +947,6 @@ hipError_t by_dag(const HopLaunch& L, hipStream_t st)
 
 // columns per thread: FP64 keeps R <= 2 (R >= 3 exceeds 256 VGPRs and spills)
 template <class P> constexpr int max_R() { return P::id == PREC_F64 ? 2 : 4; }
-
-template <class P, class PR>
-hipError_t by_R(const HopLaunch& L, hipStream_t st)
-{
-    switch (L.R) {
-    case 1: return by_dag<P, PR, 1>(L, st);
-    case 2: return by_dag<P, PR, 2>(L, st);
-    }
-    if constexpr (max_R<P>() >= 4) {
-        switch (L.R) {
-        case 3: return by_dag<P, PR, 3>(L, st);
-        case 4: return by_dag<P, PR, 4>(L, st);
-        }
-    }
-    return hipErrorInvalidValue;
-}
 
 }  // namespace dslash
 }  // namespace bq

@@ -87,6 +87,9 @@ hipError_t launch_spinor_import(const double2* canon, int ncol, const Geom& g, i
                                 hipStream_t st);
 hipError_t launch_spinor_export(FieldArg src, int ncol, const Geom& g, int parity, int prec, double2* canon,
                                 hipStream_t st);
+// distance of the canonical FP64 links from SU(3): one partial maximum per part (see link_su3_parts)
+int link_su3_parts(size_t nlinks);
+hipError_t launch_link_su3_dev(const double2* canon, size_t nlinks, double* partial, hipStream_t st);
 hipError_t launch_plaquette(const Geom& g, const double2* const U64[8], double* partial, int nparts, hipStream_t st);
 
 // BLAS-1 and reductions
@@ -103,9 +106,86 @@ hipError_t launch_accum(int xprec, FieldArg x, FieldArg y64, int Vh, int ncol, c
 // p = lowp(r64) + beta p (restart after a reliable update), rs = lowp(r64)
 hipError_t launch_restart(FieldArg r64, int rsprec, FieldArg rs, int pprec, FieldArg p, int Vh, int ncol,
                           const double* beta, const int* flag, hipStream_t st);
+// <x, y> (gamma5: <x, gamma_5 y>) per column, FP64; partials [col][re/im][wave]
 hipError_t launch_dot(int prec, FieldArg x, FieldArg y, int Vh, int ncol, double* partial, int nwaves,
-                      hipStream_t st);
+                      hipStream_t st, int gamma5 = 0);
 hipError_t launch_z2_noise(uint64_t seed, long n0, const Geom& g, int parity, FieldArg dst, int ncol,
+                           hipStream_t st);
+
+// y += a x per column (a real, the same for every column) with |y|^2 partials per wave (FP64)
+hipError_t launch_axpy_norm(FieldArg x, FieldArg y, double a, int n, int ncol, double* partial, int nwaves,
+                            hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// multishift CG: (A + sigma_k) x_k = b for all shifts in the Krylov space of the base system
+// A + sigma_b (sigma_b the smallest shift), with collinear shifted residuals r_k = zeta_k r
+// ---------------------------------------------------------------------------
+constexpr int kMaxShifts = 16;
+struct MsState {
+    // per column
+    double* rho;      // |r|^2
+    double* alpha;    // base alpha_j
+    double* alpha_prev;
+    double* beta;     // base beta_j
+    double* beta_prev;
+    double* stop2;    // (tol |b|)^2
+    int* status;      // COL_ACTIVE / COL_DONE / COL_FAILED
+    int* iters;
+    // per column and shift, index c * nshift + k
+    double* zeta;      // zeta_j
+    double* zeta_prev; // zeta_{j-1}
+    double* zeta_new;  // zeta_{j+1}
+    double* ak;        // shift alpha
+    double* bk;        // shift beta
+    int* act;          // shift still iterating
+    int* kiters;       // iterations of the shift
+    int nshift, base;
+    double shift[kMaxShifts];  // sigma_k - sigma_b
+};
+struct MsFields {
+    FieldArg r, w, p;              // base residual, A p (without the base shift), base direction
+    FieldArg x[kMaxShifts];        // solutions
+    FieldArg pk[kMaxShifts];       // shift directions (pk[base] = p)
+};
+hipError_t launch_ms_init(const MsState& s, int ncol, double tol2, hipStream_t st);
+hipError_t launch_fin_ms_alpha(const MsState& s, const double* pq, const double* pp, int nwaves, int ncol,
+                               double sigma_b, hipStream_t st);
+hipError_t launch_fin_ms_beta(const MsState& s, const double* pr, int nwaves, int ncol, hipStream_t st);
+// r -= alpha (w + sigma_b p); x_k += ak p_k (active shifts); |r|^2 partials
+hipError_t launch_ms_update1(const MsState& s, const MsFields& f, double sigma_b, int n, int ncol, double* partial,
+                             int nwaves, hipStream_t st);
+// p_k = zeta_{j+1} r + bk p_k (active shifts other than the base); p = r + beta p; |p|^2 partials
+hipError_t launch_ms_update2(const MsState& s, const MsFields& f, int n, int ncol, double* partial, int nwaves,
+                             hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// BiCGstab on Mhat (inner precision FP64 or FP32, FP64 reductions, FP64 restarts)
+// ---------------------------------------------------------------------------
+struct BicgScalars {
+    double2* rho;     // <rhat, r>
+    double2* alpha;
+    double2* omega;
+    double2* beta;
+    double* r2;       // |r|^2 of the inner iteration
+    double* stop2;    // inner goal |r|^2
+    double* tol2b2;   // (tol |b|)^2 of the FP64 system
+    double delta2;    // inner goal relative to the last FP64 residual
+    int* status;      // COL_ACTIVE, COL_STOPPED (inner goal reached), COL_DONE, COL_FAILED
+    int* iters;
+    int* nrel;        // FP64 residual recomputations
+    int* restart;     // set by the reliable pass for columns that restart
+};
+hipError_t launch_bicg_p(int prec, FieldArg r, FieldArg p, FieldArg v, const BicgScalars& s, int n, int ncol,
+                         hipStream_t st);
+// partials of <a1, b1> and (a2.d != null) <a2, b2>, [col][re1, im1, re2, im2][wave]
+hipError_t launch_dots2(int prec, FieldArg a1, FieldArg b1, FieldArg a2, FieldArg b2, const int* status, int n,
+                        int ncol, double* partial, int nwaves, hipStream_t st);
+hipError_t launch_bicg_s(int prec, FieldArg r, FieldArg v, FieldArg s_, const BicgScalars& s, int n, int ncol,
+                         hipStream_t st);
+hipError_t launch_bicg_xr(int prec, FieldArg x, FieldArg p, FieldArg s_, FieldArg t, FieldArg r, FieldArg rhat,
+                          const BicgScalars& s, int n, int ncol, double* partial, int nwaves, hipStream_t st);
+// step 0: alpha, 1: omega, 2: rho / beta / stop test, 3: reliable pass decision (partials of |r64|^2)
+hipError_t launch_fin_bicg(int step, const BicgScalars& s, const double* partial, int nwaves, int ncol,
                            hipStream_t st);
 
 // CG finalisation kernels (one block per column)

@@ -26,8 +26,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 
 
 # the sources that define the stencil kernels (host-side library code does not change them)
-KERNEL_SOURCES = ("bq_device.h", "bq_kernels.h", "bq_dslash_impl.h", "bq_dslash_f64.hip", "bq_dslash_f32.hip",
-                  "bq_dslash_f16.hip")
+KERNEL_SOURCES = ("bq_device.h", "bq_kernels.h", "bq_dslash_impl.h", "bq_dslash_inst.hip")
 
 
 def source_digest():

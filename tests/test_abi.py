@@ -47,7 +47,7 @@ def test_binding_covers_header():
 def test_argument_validation_without_device(lib):
     from paper_1711_03836_amd import bqhip as b
     assert b.bq_version() >= 10000
-    assert b.bq_context_create(0, 0, None) == b.BQ_ERR_INVALID
+    assert b.bq_context_create(0, 0, b.ALLOC_FN(), b.DEALLOC_FN(), None, None) == b.BQ_ERR_INVALID
     assert b"NULL" in b.bq_last_error()
     assert b.bq_gauge_upload(None, None, None, 0, -1, None) == b.BQ_ERR_INVALID
     assert b.bq_field_create(None, None, 0, 0, 1, None) == b.BQ_ERR_INVALID

@@ -90,3 +90,156 @@ def test_server_device_buffers(world):
         assert rc_h == rc_d == bq.BQ_OK
         assert isinstance(x_d, torch.Tensor) and x_d.is_cuda
         assert np.array_equal(x_h, x_d.cpu().numpy())
+
+
+def test_server_full_residual_reported(world):
+    """full_rel_resid of a served request is |b - M x| / |b| on the full lattice: the oracle recomputes it
+    from the returned solution."""
+    bq, ctx, G = world
+    b = inputs.gaussian_spinor(DIMS_A, 2, seed=510)
+    out = serve(bq, ctx, [(DIMS_A, G[DIMS_A][0], b, 0.1215, 1)])
+    rc, info, x = out[0]
+    assert rc == bq.BQ_OK
+    ref = orc.Operator(DIMS_A, G[DIMS_A][1], 0.1215, 1.5)
+    for c in range(2):
+        rel = np.linalg.norm(b[c] - ref.M(x[c])) / np.linalg.norm(b[c])
+        print(f"[serve] column {c}: oracle |b - Mx|/|b| {rel:.3e}, reported {info[c]['full_rel_resid']:.3e}",
+              flush=True)
+        assert abs(rel - info[c]["full_rel_resid"]) <= 0.01 * rel + 1e-15
+
+
+def test_server_bad_request_isolated(world):
+    """A request whose clover is not positive definite finishes with BQ_ERR_CLOVER_NOT_HPD at admission;
+    the requests around it complete and match their results alone."""
+    bq, ctx, G = world
+    g = G[DIMS_A][0]
+    good = [inputs.gaussian_spinor(DIMS_A, 1, seed=520 + i) for i in range(3)]
+    srv = bq.Server(ctx, 8, 8)
+    t0 = srv.submit(g, good[0], 0.12, 1.5)
+    tbad = srv.submit(g, inputs.gaussian_spinor(DIMS_A, 1, seed=529), 4.0, 20.0)
+    t1 = srv.submit(g, good[1], 0.121, 1.5)
+    t2 = srv.submit(g, good[2], 0.122, 1.5)
+    res = {}
+    for _ in range(1000):
+        for t in srv.step():
+            res[t] = srv.result(t)
+        if len(res) == 4:
+            break
+    srv.close()
+    assert res[tbad][0] == bq.BQ_ERR_CLOVER_NOT_HPD
+    for t, b, k in ((t0, good[0], 0.12), (t1, good[1], 0.121), (t2, good[2], 0.122)):
+        rc, info, x = res[t]
+        assert rc == bq.BQ_OK and info[0]["converged"]
+        alone = serve(bq, ctx, [(DIMS_A, g, b, k, 1)])[0]
+        assert np.array_equal(alone[2], x)
+
+
+def _run_to_done(srv, tickets, limit=2000):
+    res = {}
+    for _ in range(limit):
+        for t in srv.step():
+            res[t] = srv.result(t)
+        if len(res) == len(tickets):
+            return res
+    raise AssertionError("server did not finish")
+
+
+def test_server_admission_by_hbm_budget():
+    """With a context budget that holds the session and one request's operator but not two, the second
+    request waits until the first retires, then completes bitwise equal to its result alone."""
+    from paper_1711_03836_amd import bqhip as bq
+    U = inputs.gauge_field(DIMS_A, 0.2, seed=61)
+    ba = inputs.gaussian_spinor(DIMS_A, 1, seed=540)
+    bb = inputs.gaussian_spinor(DIMS_A, 1, seed=541)
+    # measure: everything held while one request runs, and after it retires (the operator freed)
+    big = bq.Context(0)
+    g = bq.Gauge(big, DIMS_A, U)
+    srv = bq.Server(big, 4, 4)
+    ta = srv.submit(g, ba, 0.12, 1.5)
+    srv.step()
+    assert srv.pending() == (0, 1)
+    used_running = big.hbm_used()
+    alone_a = _run_to_done(srv, [ta])
+    used_idle = big.hbm_used()
+    tb = srv.submit(g, bb, 0.121, 1.5)
+    alone_b = _run_to_done(srv, [tb])
+    op_bytes = used_running - used_idle
+    assert op_bytes > 0
+    srv.close()
+    srv = None
+    # the same work under a budget with room for 1.5 operators
+    ctx = bq.Context(0, hbm_budget=used_idle + op_bytes * 3 // 2)
+    g2 = bq.Gauge(ctx, DIMS_A, U)
+    srv = bq.Server(ctx, 4, 4)
+    ta = srv.submit(g2, ba, 0.12, 1.5)
+    tb = srv.submit(g2, bb, 0.121, 1.5)
+    srv.step()
+    assert srv.pending() == (1, 1)  # b waits for memory, not for slots (4 slots, 2 columns)
+    res = _run_to_done(srv, [ta, tb])
+    assert res[ta][0] == res[tb][0] == bq.BQ_OK
+    assert np.array_equal(res[ta][2], alone_a[ta][2])
+    assert np.array_equal(res[tb][2], alone_b[tb][2])
+    srv.close()
+
+
+def test_server_release_and_gauge_replacement():
+    """Sessions hold their gauge field: freeing it is BQ_ERR_BUSY until bq_server_release; a new field
+    of other extents then serves correctly on the same server."""
+    from paper_1711_03836_amd import bqhip as bq
+    ctx = bq.Context(0)
+    U = inputs.gauge_field(DIMS_A, 0.2, seed=61)
+    g = bq.Gauge(ctx, DIMS_A, U)
+    srv = bq.Server(ctx, 4, 8)
+    t = srv.submit(g, inputs.gaussian_spinor(DIMS_A, 1, seed=550), 0.12, 1.5)
+    with pytest.raises(bq.BqError) as e:
+        srv.release(g)  # the request is still queued
+    assert e.value.code == bq.BQ_ERR_BUSY
+    _run_to_done(srv, [t])
+    with pytest.raises(bq.BqError) as e:
+        g.close()
+    assert e.value.code == bq.BQ_ERR_BUSY
+    held = ctx.hbm_used()
+    srv.release(g)
+    assert ctx.hbm_used() < held
+    g.close()
+    U2 = inputs.gauge_field(DIMS_B, 0.2, seed=62)
+    g2 = bq.Gauge(ctx, DIMS_B, U2)
+    b = inputs.gaussian_spinor(DIMS_B, 2, seed=551)
+    t = srv.submit(g2, b, 0.121, 1.5)
+    rc, info, x = _run_to_done(srv, [t])[t]
+    assert rc == bq.BQ_OK
+    ref = orc.Operator(DIMS_B, U2, 0.121, 1.5)
+    for c in range(2):
+        assert np.linalg.norm(b[c] - ref.M(x[c])) / np.linalg.norm(b[c]) < 1e-7
+    srv.close()
+
+
+def test_server_backfill_order(world):
+    """A wide request that does not fit waits; with backfill a later narrow request passes it, with
+    backfill 0 (strict arrival order) it does not."""
+    bq, ctx, G = world
+    g = G[DIMS_A][0]
+    first = {}
+    for backfill in (0, 8):
+        srv = bq.Server(ctx, 4, 4)
+        srv.set_backfill(backfill)
+        done = {}
+
+        def step():
+            for t in srv.step():
+                done[t] = srv.result(t)
+        t_hold = srv.submit(g, inputs.gaussian_spinor(DIMS_A, 2, seed=560), 0.12, 1.5)
+        step()  # the 2-column request now holds 2 of the 4 slots
+        t_wide = srv.submit(g, inputs.gaussian_spinor(DIMS_A, 3, seed=561), 0.12, 1.5)
+        t_narrow = srv.submit(g, inputs.gaussian_spinor(DIMS_A, 1, seed=562), 0.12, 1.5)
+        step()
+        first[backfill] = srv.pending()
+        for _ in range(2000):
+            if len(done) == 3:
+                break
+            step()
+        assert sorted(done) == sorted([t_hold, t_wide, t_narrow])
+        assert all(v[0] == bq.BQ_OK for v in done.values())
+        srv.close()
+    assert first[0] == (2, 1)  # strict order: the narrow request waits behind the wide one
+    assert first[8] == (1, 2)  # backfill: the narrow request runs beside the holder
