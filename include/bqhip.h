@@ -326,9 +326,15 @@ int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void*
  * and keeps the backward time hop of each plane from the forward time hop two
  * planes earlier (up to bs/64 column groups per workgroup).  It applies to
  * lattices whose (x,y) planes hold whole 64-site tiles and whose L_t it divides;
- * elsewhere the plain stencil runs.  Results do not depend on the configuration. */
-int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march);
-int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march);
+ * elsewhere the plain stencil runs.  lds: 1 selects the tile-shared stencil when a tile has
+ * several column groups (nrhs > R): one 64-site tile per workgroup with up to bs/64 (at most 16)
+ * column-group waves, whose links (rebuilt to 3x3) and clover are staged in LDS once and read
+ * from there by every wave (march is then ignored; bs may be any multiple of 64 up to 1024);
+ * lds: 2 is the same with R = 1 only, where each wave also takes the x and y neighbours that
+ * lie in its own tile from the other lanes' registers instead of from memory.
+ * Results do not depend on the configuration. */
+int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march, int* lds);
+int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march, int lds);
 /* Time the candidate configurations for (op's lattice, prec, nrhs) on op and keep the fastest. */
 int bq_autotune(bq_op op, int prec, int nrhs);
 

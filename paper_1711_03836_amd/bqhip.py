@@ -115,8 +115,8 @@ _sig = {
                                       _P(bq_solve_info)]),
     "bq_solve_stats_get": (C.c_int, [_h, _P(bq_solve_stats)]),
     "bq_time_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_int, C.c_void_p, _P(C.c_double), _P(C.c_double)]),
-    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
-    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
+    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
     "bq_server_create": (C.c_int, [_h, C.c_int, C.c_int, _P(_h)]),
     "bq_server_set_backfill": (C.c_int, [_h, C.c_int]),
@@ -209,13 +209,13 @@ class Context:
         return v.value
 
     def tune_get(self, prec, nrhs):
-        """(recon, R, bs, march) of the stencil for this precision and column count."""
-        r, R, bs, m = C.c_int(), C.c_int(), C.c_int(), C.c_int()
-        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs), C.byref(m)))
-        return r.value, R.value, bs.value, m.value
+        """(recon, R, bs, march, lds) of the stencil for this precision and column count."""
+        r, R, bs, m, l = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs), C.byref(m), C.byref(l)))
+        return r.value, R.value, bs.value, m.value, l.value
 
-    def tune_set(self, prec, nrhs, recon, R, bs, march=0):
-        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs, march))
+    def tune_set(self, prec, nrhs, recon, R, bs, march=0, lds=0):
+        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs, march, lds))
 
     def save_tuning(self, path, keys, lattice=None):
         """Write the stencil configurations of the (prec, nrhs) pairs in `keys` to a JSON file,
@@ -230,8 +230,7 @@ class Context:
             doc = json.load(f)
         keys = []
         for e in doc["entries"]:
-            recon, R, bs, march = e["config"]
-            self.tune_set(e["prec"], e["nrhs"], recon, R, bs, march)
+            self.tune_set(e["prec"], e["nrhs"], *e["config"])
             keys.append((e["prec"], e["nrhs"]))
         return keys
 
@@ -289,10 +288,8 @@ class Gauge:
         # collected in arbitrary order): those free it when they close
         try:
             self.close()
-        except BqError as e:
-            self._close_pending = e.code == BQ_ERR_BUSY
-        except Exception:
-            pass
+        except Exception as e:  # (module globals may already be gone at interpreter exit)
+            self._close_pending = getattr(e, "code", None) == -6  # BQ_ERR_BUSY
 
 
 class Op:

@@ -102,6 +102,7 @@ static int fail(int code, const char* fmt, ...)
 struct Tune {
     int recon, R, bs;
     int march = 0;  // > 0: t-marching stencil with segments of this many time planes, where the lattice allows
+    int lds = 0;    // 1: tile-shared stencil (links and clover staged in LDS) for several column groups per tile
 };
 
 struct bq_context_s {
@@ -400,6 +401,7 @@ static HopLaunch hop_base(bq_op op, int prec, const Tune& t, int dagger, int out
     L.R = std::min(t.R, std::max(ncol, 1));
     L.bs = t.bs;
     L.march = (t.march > 0 && G->g.blocked && G->g.L[3] % t.march == 0) ? t.march : 0;
+    L.lds = t.lds;
     L.dagger = dagger;
     L.g = G->g;
     L.parity = out_parity;
@@ -2210,26 +2212,30 @@ int bq_trace_estimators(bq_op op, uint64_t seed, int nnoise, int block, const bq
     return BQ_OK;
 }
 
-int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march)
+int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march, int* lds)
 {
-    if (!ctx || !recon || !R || !bs || !march) return fail(BQ_ERR_INVALID, "NULL argument");
+    if (!ctx || !recon || !R || !bs || !march || !lds) return fail(BQ_ERR_INVALID, "NULL argument");
     Tune t = get_tune(ctx, prec, nrhs);
     *recon = t.recon;
     *R = t.R;
     *bs = t.bs;
     *march = t.march;
+    *lds = t.lds;
     return BQ_OK;
 }
 
-int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march)
+int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march, int lds)
 {
     if (!ctx) return fail(BQ_ERR_INVALID, "NULL argument");
     const int rprec = prec == PREC_F64 ? PREC_F64 : PREC_F32;
     if (!hop_variant_exists(prec, rprec, recon, R, EPI_TV) || R > nrhs)
         return fail(BQ_ERR_INVALID, "no kernel variant for prec %d recon %d R %d (nrhs %d)", prec, recon, R, nrhs);
-    if (bs != 64 && bs != 128 && bs != 256 && bs != 512) return fail(BQ_ERR_INVALID, "bs must be 64, 128, 256 or 512");
+    if (bs != 64 && bs != 128 && bs != 256 && bs != 512 && !(lds && bs % 64 == 0 && bs <= 1024))
+        return fail(BQ_ERR_INVALID, "bs must be 64, 128, 256 or 512 (with lds: a multiple of 64 up to 1024)");
     if (march < 0) return fail(BQ_ERR_INVALID, "march must be >= 0");
-    ctx->tune[{prec, nrhs}] = Tune{recon, R, bs, march};
+    if (lds < 0 || lds > 2) return fail(BQ_ERR_INVALID, "lds must be 0, 1 or 2");
+    if (lds == 2 && R != 1) return fail(BQ_ERR_INVALID, "lds 2 (lane exchange) takes one column per thread");
+    ctx->tune[{prec, nrhs}] = Tune{recon, R, bs, march, lds};
     return BQ_OK;
 }
 
@@ -2267,7 +2273,23 @@ int bq_autotune(bq_op op, int prec, int nrhs)
                 for (int bs : {64, 128, 256, 512}) {
                     if (!hop_variant_exists(prec, rprec, recon, R, EPI_TINV)) continue;
                     if (recon == 12 && !op->gauge->get(prec, 12)) continue;  // not an SU(3) field
-                    const Tune t{recon, R, bs, march};
+                    const Tune t{recon, R, bs, march, 0};
+                    const double ms = time_of(t, 5);
+                    if (ms < 1e300) cand.push_back({ms, t});
+                }
+    // tile-shared kernel: one tile per workgroup (no marching), several column groups per tile
+    // (R < nrhs), at most 2 columns per thread, bs / 64 waves per workgroup at most; mode 2 (lane
+    // exchange of x and y neighbours) with one column per thread and a whole tile's columns
+    for (int recon : {12, 18})
+        for (int R = 1; R <= std::min(nrhs - 1, 2); R++)
+            for (int waves : {4, 6, 8, 12, 16})
+                for (int mode : {1, 2}) {
+                    if (!hop_variant_exists(prec, rprec, recon, R, EPI_TINV)) continue;
+                    if (recon == 12 && !op->gauge->get(prec, 12)) continue;
+                    const int G = (nrhs + R - 1) / R;
+                    if (waves > G && waves != 4) continue;  // bs / 64 is only a bound on the waves
+                    if (mode == 2 && (R != 1 || waves < std::min(G, 16))) continue;
+                    const Tune t{recon, R, 64 * waves, 0, mode};
                     const double ms = time_of(t, 5);
                     if (ms < 1e300) cand.push_back({ms, t});
                 }
@@ -2276,8 +2298,8 @@ int bq_autotune(bq_op op, int prec, int nrhs)
         return fail(BQ_ERR_DEVICE, "no kernel configuration could be timed");
     }
     // pass 2: the configurations within 10% of the fastest, timed again over more launches; of those
-    // within 2% of the new fastest the first in (march, recon, R, bs) order wins, so near-ties resolve
-    // the same way from run to run
+    // within 2% of the new fastest the first in candidate order wins (plain and marching kernels by
+    // (march, recon, R, bs), then the tile-shared ones), so near-ties resolve the same way from run to run
     double best = 1e300;
     for (auto& c : cand) best = std::min(best, c.first);
     std::vector<std::pair<double, Tune>> fin;

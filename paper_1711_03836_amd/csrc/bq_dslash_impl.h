@@ -11,6 +11,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bq_kernels.h"
 
@@ -307,6 +308,23 @@ __device__ __forceinline__ void load_clover_block(const typename P::unit* __rest
 #endif
 }
 
+// the same block from a tile's clover copy in LDS, laid out [unit][lane]
+template <class P>
+__device__ __forceinline__ void load_clover_block_lds(const typename P::unit* S, int lane, int blk,
+                                                      cx<typename P::real> (&c)[18])
+{
+    if constexpr (P::id == PREC_F16) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) CxIO<P16, 2>::unpack(S[(blk * 9 + k) * kTile + lane], c[2 * k], c[2 * k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+            const auto t = S[(blk * 18 + k) * kTile + lane];
+            c[k] = {t.x, t.y};
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void clover_mul(const cx<T> (&c)[18], const cx<T>* x, cx<T>* y)
 {
@@ -533,8 +551,14 @@ __device__ __forceinline__ void hop_all(const Args<P, PR>& A, const Site& s, con
 // no active column pass nrm = 0 to the wave reduction.
 template <class P, class PR, int R, int EPI, bool PC, int LA>
 __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool (&act)[R], bool any, int c0,
-                                         cx<typename P::real> (&acc)[R][12])
+                                         cx<typename P::real> (&acc)[R][12],
+                                         const typename P::unit* sclov = nullptr)
 {
+    // the tile's clover from LDS when the workgroup staged it (shared clover only)
+    auto clover_block = [&](const typename P::unit* C, int blk, cx<typename P::real>(&cb)[18]) {
+        if (!PC && sclov != nullptr) load_clover_block_lds<P>(sclov, j & (kTile - 1), blk, cb);
+        else load_clover_block<P, PC ? kBufNT : LA>(C, j, blk, cb);
+    };
     using T = typename P::real;
     using TR = typename PR::real;
     constexpr int CA = PC ? kBufNT : LA;  // per-column clover is read by one wave only
@@ -562,7 +586,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 #pragma unroll
             for (int blk = 0; blk < 2; blk++) {
                 cx<T> cb[18];
-                if constexpr (!PC) load_clover_block<P, CA>(A.clov, j, blk, cb);
+                if constexpr (!PC) clover_block(A.clov, blk, cb);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     if (!act[r]) continue;
@@ -583,7 +607,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 #pragma unroll
         for (int blk = 0; blk < 2; blk++) {
             cx<T> cb[18];
-            if constexpr (!PC) load_clover_block<P, CA>(A.clov, j, blk, cb);
+            if constexpr (!PC) clover_block(A.clov, blk, cb);
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (!act[r]) continue;
@@ -612,7 +636,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
 #pragma unroll
         for (int blk = 0; blk < 2; blk++) {
             cx<T> cb[18];
-            if constexpr (!PC) load_clover_block<P, CA>(A.clov, j, blk, cb);
+            if constexpr (!PC) clover_block(A.clov, blk, cb);
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (!act[r]) continue;
@@ -832,6 +856,275 @@ __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
     hop_item<P, PR, R, DAG, EPI, RECON, PC, LA>(A, tblk, lb - tblk * A.nch);
 }
 
+// ---------------------------------------------------------------------------
+// Tile-shared variant for several column groups per tile (tune field `lds`).
+//
+// A workgroup owns one 64-site tile and up to 16 column-group waves.  It first loads the tile's
+// 8 links per site (rebuilt to full 3x3 matrices) and, for a shared clover, the tile's clover
+// blocks into LDS, once; every wave then reads them from LDS.  The waves of the plain kernel
+// each read the same links and clover through the vector memory pipeline, whose address unit is
+// what limits a multi-column launch; here each wave issues only its neighbour-spinor loads and
+// its stores.  Per site and column the arithmetic is the plain kernel's, in the same order, so
+// the results are bitwise equal.
+// ---------------------------------------------------------------------------
+
+template <class P>
+struct LinkLds {
+    using C = typename std::conditional<sizeof(typename P::real) == 8, double2, float2>::type;
+};
+
+// LDS bytes of a tile: links (8 x 9 complex in the real type of P) + clover units (shared clover)
+template <class P, bool CLOV>
+constexpr int tile_lds_bytes()
+{
+    return 8 * 9 * kTile * (int)sizeof(typename LinkLds<P>::C) +
+           (CLOV ? clover_units<P>() * kTile * (int)sizeof(typename P::unit) : 0);
+}
+
+// Whether a launch stages the tile's clover: only epilogues that apply a clover read it (EPI_HOP
+// launches have no clover array), per-column clover is read by one wave each, and FP64 keeps its
+// clover in global memory since its links alone fill 72 KB of LDS per tile.
+template <class P, bool PC, int EPI> constexpr bool clover_in_lds() { return !PC && P::id != PREC_F64 && EPI != EPI_HOP; }
+
+// prefetch depth of the tile-shared kernel: neighbour spinors of the next NB - 1 half hops are in
+// flight while a half hop computes (its links come from LDS and need no prefetch)
+template <class P, int R> constexpr int lds_ring() { return 2; }
+
+// value of lane `src` (0..63) of the wave, for every lane (ds_bpermute through the LDS crossbar)
+__device__ __forceinline__ float lane_get(int src, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_get(int src, double v)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(src << 2, w.x),
+                                                __builtin_amdgcn_ds_bpermute(src << 2, w.y)));
+}
+
+// Half hop H (x or y direction) from the wave's own input tile: lane i holds the input-parity
+// spinor with its own checkerboard index, base + i, which for most lanes is where an x or y
+// neighbour lives.  Every lane projects its spinor with the half hop's projector and the
+// destination lane takes it from the source lane; lanes whose neighbour lies outside the tile
+// load it and project it themselves.  The arithmetic is the plain kernel's: the projection of
+// the neighbour spinor, the SU(3) product and the reconstruction, in the same order.
+template <class P, class PR, int DAG, int RECON, int H>
+__device__ __forceinline__ void hh_xchg(const Args<P, PR>& A, const Site& s, bool act, int c0, int base,
+                                        const Raw<P, 12>& own, float own_sc,
+                                        const typename LinkLds<P>::C* __restrict__ lk, int lane,
+                                        cx<typename P::real> (&acc)[12])
+{
+    using T = typename P::real;
+    constexpr int MU = H >> 1;
+    constexpr bool BW = H & 1;
+    constexpr int S = (DAG ? +1 : -1) * (BW ? -1 : +1);
+    static_assert(MU < 3, "time hops are loaded");
+    const int jn = nbr(A.g, s, MU, BW ? -1 : +1);
+    const int src = jn - base;
+    const bool in = act && (unsigned)src < (unsigned)kTile;
+    cx<T> h[6];
+    {
+        cx<T> p[12], hs[6];
+        unpack_raw<P, 12>(own, p);
+        project<T, MU, S>(p, hs);
+        const int sl = src & (kTile - 1);
+#pragma unroll
+        for (int q = 0; q < 6; q++) h[q] = {lane_get(sl, hs[q].re), lane_get(sl, hs[q].im)};
+    }
+    float hsc = 1.0f;
+    if constexpr (P::id == PREC_F16) hsc = lane_get(src & (kTile - 1), own_sc);
+    if (act && !in) {  // neighbour outside the tile: load it
+        HalfHop<P, 1, RECON> d;
+        d.jn = jn;
+        hh_load_spinor(A, c0, 0, d);
+        cx<T> p[12];
+        unpack_raw<P, 12>(d.sp[0], p);
+        project<T, MU, S>(p, h);
+        if constexpr (P::id == PREC_F16) hsc = d.sc[0];
+    }
+    PLink<P, RECON, BW> L;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const auto t = lk[(H * 9 + k) * kTile + lane];
+        L.u[k] = {(T)t.x, (T)t.y};
+    }
+    if (act) {
+        cx<T> y[6];
+        if constexpr (BW) mul_Ud(L.u, h, y);
+        else mul_U(L.u, h, y);
+        if constexpr (P::id == PREC_F16) reconstruct_add_k<T, MU, S>(acc, y, hsc);
+        else reconstruct_add<T, MU, S>(acc, y);
+    }
+    const bool a1[1] = {act};
+    cx<T>(&acc1)[1][12] = *reinterpret_cast<cx<T>(*)[1][12]>(&acc);
+    phase_end(a1, acc1);
+}
+
+template <class P, class PR, int R, int RECON, int NB, int H>
+__device__ __forceinline__ void lds_issue(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                          HalfHop<P, R, RECON> (&d)[NB])
+{
+    if constexpr (H < 8) {
+        HalfHop<P, R, RECON>& nx = d[H % NB];
+        nx.jn = nbr(A.g, s, H >> 1, (H & 1) ? -1 : +1);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (act[r]) hh_load_spinor(A, c0 + r, r, nx);
+    }
+}
+
+template <class P, class PR, int R, int DAG, int RECON, int NB, int H>
+__device__ __forceinline__ void hh_step_lds(const Args<P, PR>& A, const Site& s, const bool (&act)[R], int c0,
+                                            const typename LinkLds<P>::C* __restrict__ lk, int lane,
+                                            HalfHop<P, R, RECON> (&d)[NB], cx<typename P::real> (&acc)[R][12])
+{
+    using T = typename P::real;
+    constexpr int MU = H >> 1;
+    constexpr bool BW = H & 1;
+    constexpr int S = (DAG ? +1 : -1) * (BW ? -1 : +1);
+    lds_issue<P, PR, R, RECON, NB, H + NB - 1>(A, s, act, c0, d);
+    HalfHop<P, R, RECON>& cur = d[H % NB];
+    PLink<P, RECON, BW> L;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const auto t = lk[(H * 9 + k) * kTile + lane];
+        L.u[k] = {(T)t.x, (T)t.y};
+    }
+    T coef = T(1);
+    if constexpr (MU == 3) {
+        if constexpr (BW) coef = (s.t == 0) ? A.eb_bc : A.eb;
+        else coef = (s.t == A.g.L[3] - 1) ? A.ef_bc : A.ef;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (!act[r]) continue;
+        cx<T> y[6];
+        if constexpr (P::id == PREC_F16) {
+            hop_product<P, RECON, MU, S, BW, false>(L, cur.sp[r], T(1), y);
+            reconstruct_add_k<T, MU, S>(acc[r], y, (MU == 3) ? coef * cur.sc[r] : cur.sc[r]);
+        } else {
+            hop_product<P, RECON, MU, S, BW, MU == 3>(L, cur.sp[r], coef, y);
+            reconstruct_add<T, MU, S>(acc[r], y);
+        }
+    }
+    phase_end(act, acc);
+}
+
+template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA, bool XCHG>
+__global__ __launch_bounds__(1024) void k_hop_lds(const Args<P, PR> A)
+{
+    using T = typename P::real;
+    using LC = typename LinkLds<P>::C;
+    using U = typename P::unit;
+    constexpr bool CL = clover_in_lds<P, PC, EPI>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    LC* lk = (LC*)smem;                               // [8 half hops][9][64]
+    U* sc = (U*)(smem + 8 * 9 * kTile * sizeof(LC));  // [clover units][64]
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int lt = lb / A.nch;
+    const int chunk = lb - lt * A.nch;
+    const int tile = tile_at(A.g, lt);                // lt < ntiles: one tile per workgroup
+    const int base = tile * kTile;
+    // 1. stage the tile's links (8 half hops x 64 sites) and clover
+    for (int t = threadIdx.x; t < 8 * kTile; t += blockDim.x) {
+        const int site = t & (kTile - 1), H = t >> kTileLog;
+        const int mu = H >> 1;
+        const bool bw = H & 1;
+        const int j = base + site;
+        cx<T> u[9];
+        if (j < A.g.Vh) {
+            const Site st = site_of(A.g, A.parity, j);
+            const int jn = nbr(A.g, st, mu, bw ? -1 : +1);
+            Raw<P, link_cx<RECON>()> raw;
+            load_units<P, link_cx<RECON>(), LA>(buf_rsrc(A.U[(bw ? 1 - A.parity : A.parity) * 4 + mu]), bw ? jn : j, raw);
+            link_from_raw<P, RECON>(raw, u);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = {T(0), T(0)};
+        }
+#pragma unroll
+        for (int k = 0; k < 9; k++) lk[(H * 9 + k) * kTile + site] = LC{u[k].re, u[k].im};
+    }
+    if constexpr (CL) {
+        constexpr int NU = clover_units<P>();  // 36 (FP32) or 18 (FP16) 8-byte units, stored in pairs
+        const U* C = (const U*)A.clov + (size_t)tile * NU * kTile;
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(C);
+        for (int t = threadIdx.x; t < (NU / 2) * kTile; t += blockDim.x) {
+            const int site = t & (kTile - 1), q = t >> kTileLog;
+            const bq_u4v v = buf_load16<LA>(rs, (uint32_t)toff<U>(site, 2 * q, NU) * 8u);
+            sc[(2 * q) * kTile + site] = __builtin_bit_cast(U, bq_u2v_b{v.x, v.y});
+            sc[(2 * q + 1) * kTile + site] = __builtin_bit_cast(U, bq_u2v_b{v.z, v.w});
+        }
+    }
+    __syncthreads();
+    // 2. one column group per wave
+    const int w = threadIdx.x >> kTileLog;
+    const int lane = threadIdx.x & (kTile - 1);
+    const int j = base + lane;
+    const int c0 = __builtin_amdgcn_readfirstlane((chunk * A.gw + w) * R);
+    bool act[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int c = c0 + r;
+        act[r] = j < A.g.Vh && c < A.ncol && col_selected(A.status, A.statmask, c);
+        any |= act[r];
+    }
+    cx<T> acc[R][12];
+    if constexpr (XCHG) {
+        // x and y half hops by lane exchange from the own input tile (all lanes take part in the
+        // exchange; the wave's column is uniform), then the z and t half hops as loads
+        static_assert(R == 1, "lane exchange holds one column per wave");
+        if (c0 >= A.ncol || !col_selected(A.status, A.statmask, c0)) return;  // uniform over the wave
+        const bool act0 = act[0];
+        const Site s = site_of(A.g, A.parity, act0 ? j : base);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[0][k] = {T(0), T(0)};
+        Raw<P, 12> own;
+        float own_sc = 0.0f;
+        if (act0) {
+            HalfHop<P, 1, RECON> o;
+            o.jn = j;
+            hh_load_spinor(A, c0, 0, o);
+            own = o.sp[0];
+            if constexpr (P::id == PREC_F16) own_sc = o.sc[0];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12 / P::cpu; k++) __builtin_memset(&own.u[k], 0, sizeof(own.u[k]));
+        }
+        constexpr int NB = 2;
+        HalfHop<P, R, RECON> d[NB];
+        hh_xchg<P, PR, DAG, RECON, 0>(A, s, act0, c0, base, own, own_sc, lk, lane, acc[0]);
+        hh_xchg<P, PR, DAG, RECON, 1>(A, s, act0, c0, base, own, own_sc, lk, lane, acc[0]);
+        hh_xchg<P, PR, DAG, RECON, 2>(A, s, act0, c0, base, own, own_sc, lk, lane, acc[0]);
+        lds_issue<P, PR, R, RECON, NB, 4>(A, s, act, c0, d);
+        hh_xchg<P, PR, DAG, RECON, 3>(A, s, act0, c0, base, own, own_sc, lk, lane, acc[0]);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 4>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 5>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 6>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 7>(A, s, act, c0, lk, lane, d, acc);
+    } else if (any) {
+        const Site s = site_of(A.g, A.parity, j);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[r][k] = {T(0), T(0)};
+        constexpr int NB = lds_ring<P, R>();
+        HalfHop<P, R, RECON> d[NB];
+        lds_issue<P, PR, R, RECON, NB, 0>(A, s, act, c0, d);
+        if constexpr (NB > 2) lds_issue<P, PR, R, RECON, NB, 1>(A, s, act, c0, d);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 0>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 1>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 2>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 3>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 4>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 5>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 6>(A, s, act, c0, lk, lane, d, acc);
+        hh_step_lds<P, PR, R, DAG, RECON, NB, 7>(A, s, act, c0, lk, lane, d, acc);
+    }
+    epilogue<P, PR, R, EPI, PC, LA>(A, j, act, any, c0, acc, CL ? sc : nullptr);
+}
+
 template <class P>
 SpinorPtr<P> sp(const FieldArg& f)
 {
@@ -894,6 +1187,37 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
             hipLaunchKernelGGL((k_hop_march<P, PR, R, DAG, EPI, RECON, PC, kBufNT>), dim3(A.nblk * A.nch),
                                dim3(kTile * A.gw), 0, st, A, npos, L.march, nseg);
         return hipGetLastError();
+    }
+    if (L.lds && G > 1) {
+        // tile-shared: one tile per workgroup, up to 16 column-group waves, links (and clover) in LDS
+        constexpr bool CL = clover_in_lds<P, PC, EPI>();
+        constexpr int lds_bytes = tile_lds_bytes<P, CL>();
+        if (CL && L.clov == nullptr) return hipErrorInvalidValue;  // the epilogue needs a clover array
+        A.tpb = 1;
+        A.gw = std::min(G, std::max(1, std::min(16, L.bs / kTile)));  // bs / 64 column-group waves at most
+        A.nch = (G + A.gw - 1) / A.gw;
+        A.gw = (G + A.nch - 1) / A.nch;  // balance the chunks
+        A.nblk = L.g.ntiles;
+        // G > 1 here: the other column groups' waves of a tile read the same clover (FP64 keeps it
+        // in global memory), so loads go through the caches
+        auto launch = [&](auto kern, bool& attr) -> hipError_t {
+            if (!attr) {  // once per instantiation: allow more than 64 KB of dynamic LDS
+                const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                         lds_bytes);
+                if (e != hipSuccess) return e;
+                attr = true;
+            }
+            hipLaunchKernelGGL(kern, dim3(A.nblk * A.nch), dim3(kTile * A.gw), lds_bytes, st, A);
+            return hipGetLastError();
+        };
+        if constexpr (R == 1) {
+            if (L.lds == 2) {
+                static bool attr_x = false;
+                return launch(k_hop_lds<P, PR, R, DAG, EPI, RECON, PC, 0, true>, attr_x);
+            }
+        }
+        static bool attr = false;
+        return launch(k_hop_lds<P, PR, R, DAG, EPI, RECON, PC, 0, false>, attr);
     }
     // L.bs = sites per workgroup (a multiple of 64); at most 512 threads per workgroup
     const int tpb = std::max(1, L.bs / kTile);

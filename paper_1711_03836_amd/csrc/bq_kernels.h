@@ -38,6 +38,9 @@ struct HopLaunch {
     int bs = 256;            // sites per workgroup (a multiple of 64)
     int march = 0;           // > 0: t-marching kernel with segments of `march` time planes
                              //      (needs whole tiles per (x,y) plane and march | L_t)
+    int lds = 0;             // 1: tile-shared kernel (links and clover staged in LDS) when a tile has
+                             //    several column groups; 2: the same with one column per wave and the
+                             //    x and y neighbour spinors exchanged between lanes
     Geom g{};
     int parity = 0;          // output parity
     int ncol = 1;

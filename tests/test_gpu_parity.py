@@ -359,7 +359,7 @@ def test_march_matches_plain_and_oracle(bq, dims, march, prec, recon, R, bs):
         out = {}
         for m in (0, march):
             ctx.tune_set(prec, nrhs, recon, R, bs, m)
-            assert ctx.tune_get(prec, nrhs) == (recon, R, bs, m)
+            assert ctx.tune_get(prec, nrhs) == (recon, R, bs, m, 0)
             fi = bq.Field(ctx, dims, si, prec, nrhs)
             fo = bq.Field(ctx, dims, so, prec, nrhs)
             fi.put(psi)
@@ -426,5 +426,52 @@ def test_tuning_json_roundtrip(bq, setup, tmp_path):
     ctx2 = bq.Context(0)
     assert ctx2.load_tuning(path) == [(bq.BQ_F32, 4), (bq.BQ_F64, 1)]
     assert ctx2.tune_get(bq.BQ_F32, 4) == ctx.tune_get(bq.BQ_F32, 4)
-    assert ctx2.tune_get(bq.BQ_F64, 1) == (18, 1, 256, 0)
+    assert ctx2.tune_get(bq.BQ_F64, 1) == (18, 1, 256, 0, 0)
     ctx2.close()
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (8, 16, 8, 8)])
+@pytest.mark.parametrize("prec,recon,R,nrhs,lbs,mode", [
+    (0, 18, 1, 12, 768, 1), (0, 12, 2, 5, 256, 1), (1, 12, 1, 12, 768, 1), (1, 18, 2, 12, 384, 1),
+    (1, 12, 1, 17, 1024, 1), (1, 12, 1, 12, 256, 1), (2, 12, 1, 12, 768, 1), (2, 12, 2, 3, 64, 1),
+    (0, 18, 1, 12, 768, 2), (1, 12, 1, 12, 768, 2), (1, 18, 1, 17, 1024, 2), (1, 12, 1, 5, 192, 2),
+    (2, 12, 1, 12, 768, 2), (2, 12, 1, 3, 64, 2)])
+def test_tile_shared_matches_plain_and_oracle(bq, dims, prec, recon, R, nrhs, lbs, mode):
+    """The tile-shared stencil (links and clover staged in LDS once per tile, one column group per
+    wave, at most lbs/64 waves per workgroup: 17 columns with 16 waves take two workgroups of 9 and
+    8 waves per tile, 12 columns with 4 waves three workgroups) does each site's arithmetic in the
+    plain stencil's order: every operator kind and a solve are bitwise the plain results, and both
+    match the oracle.  Mode 2 takes the x and y neighbours from other lanes of the wave where they
+    lie in the tile (all of them on 8x16x8x8, most on 6x4x4x6, whose last tile is ragged)."""
+    U = inputs.gauge_field(dims, 0.3, seed=57)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.124, 1.5, 0.1)
+    ref = orc.Operator(dims, U, 0.124, 1.5, mu=0.1)
+    psi = inputs.gaussian_spinor(dims, nrhs, seed=58)
+    for name in MARCH_KINDS + ("MHAT", "DEO", "CLOVER_INV"):
+        kind = getattr(bq, "BQ_OP_" + name)
+        si, so = bq.OP_SUBSETS[kind]
+        out = {}
+        for lds in (0, 1):
+            ctx.tune_set(prec, nrhs, recon, R, lbs if lds else 64, 0, mode if lds else 0)
+            fi = bq.Field(ctx, dims, si, prec, nrhs)
+            fo = bq.Field(ctx, dims, so, prec, nrhs)
+            fi.put(psi)
+            op.apply(kind, fi, fo)
+            out[lds] = fo.get()
+        assert np.array_equal(out[0], out[1]), name
+        mask = {bq.BQ_EVEN: ref.parity == 0, bq.BQ_ODD: ref.parity == 1, bq.BQ_FULL: np.ones(ref.V, bool)}[so]
+        for c in sorted({0, nrhs - 1}):
+            want = oracle_apply(ref, kind, bq, psi[c])
+            assert maxrel(out[1][c][mask], want[mask]) < TOL[prec], (name, c)
+    b = inputs.gaussian_spinor(dims, nrhs, seed=59)
+    xs = {}
+    for lds in (0, 1):
+        for p in {prec, 0}:
+            ctx.tune_set(p, nrhs, recon if p == prec else 18, R if lds else min(R, 2), lbs if lds else 64, 0,
+                         mode if lds else 0)
+        x, info = _solve(bq, op, dims, b, bq.BQ_SYS_M, prec, 1e-10, nrhs)
+        assert all(c["converged"] for c in info)
+        xs[lds] = x
+    assert np.array_equal(xs[0], xs[1])
