@@ -242,6 +242,23 @@ int bq_field_get(bq_field f, double* dst, int dst_on_device, void* stream);
  * bq_gauge_upload), BQ_ERR_OOM, BQ_ERR_DEVICE. */
 int bq_apply(bq_op op, int kind, bq_field in, bq_field out, void* stream);
 
+/* Bytes of the static per-device array that holds the work fields of bq_apply_noalloc. */
+#define BQ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* bq_apply for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same kinds, fields and results as bq_apply,
+ * but the intermediate fields of M^dag M and of the Mhat kinds live in one static array of
+ * BQ_NOALLOC_SCRATCH_BYTES per device (loaded with the library on that device and held until the
+ * process ends), so the call allocates and frees nothing and never waits: it only enqueues its
+ * kernels on `stream` (NULL: the context's stream).  Every call on a device shares that device's
+ * array and leaves its intermediate there; each call writes its intermediate in full before
+ * reading it, so nothing has to start at zero.  Calls that overlap on one device (other streams,
+ * threads or contexts) race on the array: the caller orders them.  Room: per column, Mhat and
+ * Mhat^dag need one half-lattice spinor of the field's precision, Mhat^dag Mhat two, M^dag M one
+ * full-lattice spinor (plus tile padding); the other kinds need none.  Errors as bq_apply, and
+ * BQ_ERR_INVALID, with nothing enqueued, when the work fields do not fit. */
+int bq_apply_noalloc(bq_op op, int kind, bq_field in, bq_field out, void* stream);
+
 /* Solve the system params->system for all nrhs columns of b at once with a solver of the solver
  * list of section "Algorithms" (params->solver):
  *   BQ_SOLVER_CG        cg, the solver Tables 1-2 time: one fused multi-right-hand-side launch per

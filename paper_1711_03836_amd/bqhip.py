@@ -40,6 +40,7 @@ ERRORS = {-1: "BQ_ERR_INVALID", -2: "BQ_ERR_OOM", -3: "BQ_ERR_NOT_CONVERGED", -4
           -5: "BQ_ERR_CLOVER_NOT_HPD", -6: "BQ_ERR_BUSY", -7: "BQ_ERR_DEVICE", -8: "BQ_ERR_UNSUPPORTED"}
 BQ_ERR_INVALID, BQ_ERR_OOM, BQ_ERR_NOT_CONVERGED, BQ_ERR_NONFINITE = -1, -2, -3, -4
 BQ_ERR_CLOVER_NOT_HPD, BQ_ERR_BUSY, BQ_ERR_DEVICE, BQ_ERR_UNSUPPORTED = -5, -6, -7, -8
+BQ_NOALLOC_SCRATCH_BYTES = 64 << 20  # static per-device work array of bq_apply_noalloc
 
 BQ_F64, BQ_F32, BQ_F16 = 0, 1, 2
 BQ_EVEN, BQ_ODD, BQ_FULL = 0, 1, 2
@@ -106,6 +107,7 @@ _sig = {
     "bq_field_put": (C.c_int, [_h, C.c_void_p, C.c_int, C.c_void_p]),
     "bq_field_get": (C.c_int, [_h, C.c_void_p, C.c_int, C.c_void_p]),
     "bq_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_void_p]),
+    "bq_apply_noalloc": (C.c_int, [_h, C.c_int, _h, _h, C.c_void_p]),
     "bq_solve": (C.c_int, [_h, _h, _h, _P(bq_solve_params), _P(bq_solve_info), C.c_void_p]),
     "bq_trace": (C.c_int, [_h, C.c_uint64, C.c_int, C.c_int, _P(bq_solve_params), _P(C.c_double), _P(C.c_double),
                            _P(bq_solve_info)]),
@@ -302,6 +304,9 @@ class Op:
 
     def apply(self, kind, fin, fout, stream=None):
         check(bq_apply(self.h, kind, fin.h, fout.h, _stream(stream)))
+
+    def apply_noalloc(self, kind, fin, fout, stream=None):
+        check(bq_apply_noalloc(self.h, kind, fin.h, fout.h, _stream(stream)))
 
     def time_apply(self, kind, fin, fout, reps=20, stream=None):
         ms, by = C.c_double(), C.c_double()

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -349,7 +350,9 @@ static Vec field_vec(bq_field f, int first_half, int nh)
 // Field view of parity p of f (f must hold it)
 static Vec parity_vec(bq_field f, int p) { return field_vec(f, f->subset == BQ_FULL ? p : 0, 1); }
 
-static int alloc_vec(bq_context ctx, const Geom& g, int prec, int nh, int ncol, DevBuf& data, DevBuf& scale, Vec& v)
+// Strides of a work field of nh halves and ncol columns, and the bytes of its data and (FP16
+// only) scale arrays.
+static void vec_layout(const Geom& g, int prec, int nh, int ncol, Vec& v, size_t& data_bytes, size_t& scale_bytes)
 {
     v.prec = prec;
     v.nh = nh;
@@ -357,11 +360,20 @@ static int alloc_vec(bq_context ctx, const Geom& g, int prec, int nh, int ncol, 
     v.half_units = v.half_sites * spinor_nu(prec);
     v.cstride = v.half_units * nh + col_pad_units(prec);
     v.sstride = v.half_sites * nh + col_pad_scales();
-    CHK(data.alloc(ctx, v.cstride * ncol * unit_bytes(prec)));
-    v.d = data.p;
+    v.d = nullptr;
     v.s = nullptr;
-    if (prec == PREC_F16) {
-        CHK(scale.alloc(ctx, v.sstride * ncol * sizeof(float)));
+    data_bytes = v.cstride * ncol * unit_bytes(prec);
+    scale_bytes = prec == PREC_F16 ? v.sstride * ncol * sizeof(float) : 0;
+}
+
+static int alloc_vec(bq_context ctx, const Geom& g, int prec, int nh, int ncol, DevBuf& data, DevBuf& scale, Vec& v)
+{
+    size_t db = 0, sb = 0;
+    vec_layout(g, prec, nh, ncol, v, db, sb);
+    CHK(data.alloc(ctx, db));
+    v.d = data.p;
+    if (sb) {
+        CHK(scale.alloc(ctx, sb));
         v.s = scale.as<float>();
     }
     return BQ_OK;
@@ -1252,6 +1264,40 @@ int bq_version(void) { return 10000; }
 
 const char* bq_last_error(void) { return g_err.c_str(); }
 
+// ---------------------------------------------------------------------------
+// static work memory of the allocation-free apply
+// ---------------------------------------------------------------------------
+
+// One copy per device, loaded with the library's code object and held until the process ends.
+// Host code never uses this name as an address (on the host it only stands for the symbol): the
+// device address of each device's copy comes from hipGetSymbolAddress, taken once per device at
+// context creation and kept in scratch_base.
+static __device__ __align__(256) unsigned char scratch[BQ_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex scratch_mu;
+static std::vector<void*> scratch_base;  // per device ordinal
+
+// Take the address of the current device's copy of `scratch` (device `device` must be current).
+static int scratch_resolve(int device)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if ((int)scratch_base.size() <= device) scratch_base.resize(device + 1, nullptr);
+    if (scratch_base[device]) return BQ_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(BQ_ERR_DEVICE, "no device address for the static work array on device %d: %s", device,
+                    hipGetErrorString(e));
+    scratch_base[device] = p;
+    return BQ_OK;
+}
+
+static void* scratch_on(int device)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return device < (int)scratch_base.size() ? scratch_base[device] : nullptr;
+}
+
 int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_alloc_fn alloc, bq_dealloc_fn dealloc,
                       void* alloc_ctx, bq_context* out)
 {
@@ -1263,6 +1309,7 @@ int bq_context_create(int device, uint64_t hbm_budget_bytes, bq_alloc_fn alloc, 
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(BQ_ERR_INVALID, "device %d out of range (%d devices)", device, n);
     HIPCHK(hipSetDevice(device));
+    CHK(scratch_resolve(device));
     auto c = std::make_unique<bq_context_s>();
     c->device = device;
     size_t fr = 0, tot = 0;
@@ -1684,6 +1731,52 @@ int bq_apply(bq_op op, int kind, bq_field in, bq_field out, void* stream)
     int rc = apply_impl(op, kind, in, out, st, scr);
     if (scr.a.d || scr.b.d) HIPCHK(hipStreamSynchronize(st));  // scratch is freed on return
     return rc;
+}
+
+// Work fields apply_impl needs for an operator kind: how many, and of how many halves.
+static void apply_work_fields(int kind, int& n, int& nh)
+{
+    n = 0;
+    nh = 1;
+    switch (kind) {
+    case BQ_OP_MDAGM: n = 1; nh = 2; break;
+    case BQ_OP_MHAT: case BQ_OP_MHATDAG: n = 1; break;
+    case BQ_OP_MHATDAG_MHAT: n = 2; break;
+    }
+}
+
+int bq_apply_noalloc(bq_op op, int kind, bq_field in, bq_field out, void* stream)
+{
+    CHK(apply_check(op, kind, in, out));
+    bq_context ctx = op->gauge->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    char* base = (char*)scratch_on(ctx->device);
+    if (!base) return fail(BQ_ERR_DEVICE, "static work array of device %d not resolved", ctx->device);
+    int n = 0, nh = 1;
+    apply_work_fields(kind, n, nh);
+    // the work fields one after the other, each array on a 256-byte boundary
+    Scratch scr;
+    Vec* v[2] = {&scr.a, &scr.b};
+    size_t at[2][2] = {}, end = 0;
+    for (int i = 0; i < n; i++) {
+        size_t db = 0, sb = 0;
+        vec_layout(op->gauge->g, in->prec, nh, in->nrhs, *v[i], db, sb);
+        at[i][0] = end;
+        end += (db + 255) & ~(size_t)255;
+        at[i][1] = end;
+        end += (sb + 255) & ~(size_t)255;
+    }
+    if (end > (size_t)BQ_NOALLOC_SCRATCH_BYTES)
+        return fail(BQ_ERR_INVALID,
+                    "operator kind %d with %d columns on this lattice needs %zu bytes of work fields; the "
+                    "allocation-free apply has %llu",
+                    kind, in->nrhs, end, (unsigned long long)BQ_NOALLOC_SCRATCH_BYTES);
+    for (int i = 0; i < n; i++) {
+        v[i]->d = base + at[i][0];
+        v[i]->s = in->prec == PREC_F16 ? (float*)(base + at[i][1]) : nullptr;
+    }
+    hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
+    return apply_impl(op, kind, in, out, st, scr);  // work fields set: apply_impl allocates nothing
 }
 
 static double apply_bytes(bq_op op, int kind, int prec, int ncol, int recon)
