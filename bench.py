@@ -87,6 +87,7 @@ def main():
     for prec in {inner, 0}:
         op.autotune(prec, nrhs)
         log(f"[bench]   tune prec={prec}: recon/R/bs = {ctx.tune_get(prec, nrhs)}")
+    prefer_profiled_tune(bq, ctx, op, dims, args.inner, inner, nrhs)
 
     def solve(prec):
         rc, info = op.solve(fb, fx, tol, system=bq.BQ_SYS_M, inner_prec=prec, chunk=args.chunk,
@@ -208,6 +209,33 @@ def main():
                   "bytes_per_solve": last_st["bytes"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def prefer_profiled_tune(bq, ctx, op, dims, inner, prec, nrhs):
+    """Where the committed counter summary of K1 was taken on the current kernel sources with another
+    configuration than the autotuner's pick, and that configuration is within 2% of the pick on this
+    GPU (autotuning noise), use it, so that the timed kernel is the one whose HBM traffic was counted."""
+    import torch
+    from paper_1711_03836_amd import inputs
+    from paper_1711_03836_amd.profile_summary import source_digest
+    path = os.path.join(ROOT, "profiles", f"k1_{inner}x{nrhs}_{'x'.join(map(str, dims))}_traffic.json")
+    if not os.path.exists(path):
+        return
+    rec = json.load(open(path))
+    picked = list(ctx.tune_get(prec, nrhs))
+    if rec.get("source_digest") != source_digest() or not rec.get("tune") or list(rec["tune"]) == picked:
+        return
+    fo = bq.Field(ctx, dims, bq.BQ_ODD, prec, nrhs)
+    fe = bq.Field(ctx, dims, bq.BQ_EVEN, prec, nrhs)
+    fo.put(inputs.gaussian_spinor(dims, nrhs, seed=5))
+    stream = torch.cuda.Stream()
+    t_pick = op.time_apply(bq.BQ_OP_K1, fo, fe, reps=20, stream=stream)[0]
+    ctx.tune_set(prec, nrhs, *rec["tune"])
+    t_prof = op.time_apply(bq.BQ_OP_K1, fo, fe, reps=20, stream=stream)[0]
+    if t_prof > 1.02 * t_pick:
+        ctx.tune_set(prec, nrhs, *picked)
+    log(f"[bench]   K1 {picked}: {t_pick:.3f} ms, profiled {rec['tune']}: {t_prof:.3f} ms -> "
+        f"using {list(ctx.tune_get(prec, nrhs))}")
 
 
 def measured_traffic(dims, inner, nrhs, tune):

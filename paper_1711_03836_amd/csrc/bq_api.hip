@@ -2382,6 +2382,7 @@ int bq_autotune(bq_op op, int prec, int nrhs)
                     const int G = (nrhs + R - 1) / R;
                     if (waves > G && waves != 4) continue;  // bs / 64 is only a bound on the waves
                     if (mode == 2 && (R != 1 || waves < std::min(G, 16))) continue;
+                    if (prec == PREC_F64 && R > 1) continue;  // spills under the 1024-thread bound
                     const Tune t{recon, R, 64 * waves, 0, mode};
                     const double ms = time_of(t, 5);
                     if (ms < 1e300) cand.push_back({ms, t});

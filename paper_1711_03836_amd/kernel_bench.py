@@ -28,7 +28,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=12)
     ap.add_argument("--kind", default="K1")
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--tune", default="auto", help="'auto' or recon,R,bs[,march]")
+    ap.add_argument("--tune", default="auto", help="'auto' or recon,R,bs[,march[,lds]]")
     ap.add_argument("--eps", type=float, default=0.2)
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--stream-mib", type=int, default=0, help="measure read / write / copy bandwidth of plain "
