@@ -9,8 +9,14 @@ FP64, without blocking, fusion or reordering:
                     "Algorithms"; RHMC's rational functions need (W^dag W + b_k)^-1 for all
                     shifts b_k): one plain CG per shift on (Mhat^dag Mhat + sigma_k) x_k = b.
   - bicgstab        BiCGstab of the solver list, in van der Vorst's form, on Mhat x = b.
-  - block_cg        the "block ... cg" of the solver list: O'Leary's block CG on
-                    Mhat^dag Mhat X = B with the N x N step matrices solved densely.
+  - block_cg        the block part of the solver list's "block multishift cg": O'Leary's block CG
+                    on Mhat^dag Mhat X = B with the N x N step matrices solved densely.
+  - block_multishift_cg
+                    the solver list's "block multishift cg": block CG on the base system
+                    A + sigma_0 (sigma_0 the smallest shift) whose block residuals serve every
+                    shift, R_k^sigma = R_k xi_k^sigma with N x N matrices xi (the block form of
+                    the shifted-CG collinearity); each shift gets its own step matrices from the
+                    base ones.
   - trace_terms     the per-noise terms of the traces of section "Measurements"
                     (Tr M^-1, Tr gamma_5 M^-1, Tr (M^dag M)^-1) and of the abstract's
                     reweighting traces Tr(M^-1 dM/dp) for p = kappa, c_SW, mu.
@@ -139,6 +145,76 @@ def block_cg(op, B, tol, maxiter=100000):
         RR = RR_new
     assert X.shape[1:] == shape
     return X, -1
+
+
+def block_multishift_cg(op, B, shifts, tol, maxiter=100000):
+    """Block CG for (Mhat^dag Mhat + sigma_s) X_s = B, all shifts s and the N columns of B
+    (shape (N, V, 4, 3)) in one block Krylov space.
+
+    The base system A' = A + sigma_0 (sigma_0 = min shifts) runs O'Leary's block CG,
+        alpha_k = (P^dag A' P)^-1 (R^dag R),  X += P alpha_k,  R' = R - A' P alpha_k,
+        beta_k = (R^dag R)^-1 (R'^dag R'),  P = R' + P beta_k.
+    Its residual blocks satisfy the three-term relation
+        A' R_k = -R_{k+1} alpha_k^-1 + R_k (alpha_k^-1 + C_k) - R_{k-1} C_k,  C_k = alpha_{k-1}^-1 beta_{k-1},
+    and for a shift d = sigma_s - sigma_0 the block-CG residuals of A' + d are R_k xi_k (the same
+    Galerkin conditions).  Matching the two three-term relations column block by column block gives
+        (alpha^d_k)^-1 = xi_k^-1 (alpha_k^-1 + C_k + d) xi_k - xi_{k-1}^-1 C_k xi_k   (k = 0: alpha_0^-1 + d),
+        beta^d_{k-1} = alpha^d_{k-1} xi_{k-1}^-1 C_k xi_k,
+        P^d_k = R_k xi_k + P^d_{k-1} beta^d_{k-1},  X^d += P^d_k alpha^d_k,
+        xi_{k+1} = alpha_k^-1 xi_k alpha^d_k,        xi_0 = 1.
+    Stops when every shift's every column has |R xi e_c| <= tol |b_c| (the base, the smallest shift,
+    is last).  Returns ([X_s for s in shifts], iterations); iterations = -1 if maxiter was reached."""
+    A = normal_op(op)
+    N = B.shape[0]
+    s0 = min(shifts)
+    inv = np.linalg.inv
+    eye = np.eye(N, dtype=complex)
+
+    def gram(Xs, Ys):  # G[i, j] = <X_i, Y_j>
+        return np.array([[_dot(Xs[i], Ys[j]) for j in range(N)] for i in range(N)])
+
+    def comb(Ps, m):  # column j of the result = sum_i Ps[i] m[i, j]
+        return np.einsum("i...,ij->j...", Ps, m)
+
+    bn2 = np.array([np.real(_dot(B[c], B[c])) for c in range(N)])
+    R = B.copy()
+    P = R.copy()
+    RR = gram(R, R)
+    Xs = [np.zeros_like(B) for _ in shifts]
+    Ps = [B.copy() for _ in shifts]
+    xi = [eye.copy() for _ in shifts]
+    xi_prev = [None] * len(shifts)
+    a_prev_s = [None] * len(shifts)
+    a_prev = b_prev = None
+    for it in range(1, maxiter + 1):
+        Q = np.stack([A(P[c]) for c in range(N)]) + s0 * P
+        a = np.linalg.solve(gram(P, Q), RR)
+        for s, sig in enumerate(shifts):
+            d = sig - s0
+            if it == 1:
+                a_s = inv(inv(a) + d * eye)
+            else:
+                C = inv(a_prev) @ b_prev
+                a_s = inv(inv(xi[s]) @ (inv(a) + C + d * eye) @ xi[s] - inv(xi_prev[s]) @ C @ xi[s])
+                b_s = a_prev_s[s] @ inv(xi_prev[s]) @ C @ xi[s]
+                Ps[s] = comb(R, xi[s]) + comb(Ps[s], b_s)
+            Xs[s] = Xs[s] + comb(Ps[s], a_s)
+            xi_prev[s], a_prev_s[s] = xi[s], a_s
+            xi[s] = inv(a) @ xi[s] @ a_s
+        R = R - comb(Q, a)
+        RR_new = gram(R, R)
+        done = True
+        for s in range(len(shifts)):
+            for c in range(N):
+                v = xi[s][:, c]
+                if np.real(np.vdot(v, RR_new @ v)) > tol * tol * bn2[c]:
+                    done = False
+        if done:
+            return Xs, it
+        b = np.linalg.solve(RR, RR_new)
+        P = R + comb(P, b)
+        a_prev, b_prev, RR = a, b, RR_new
+    return Xs, -1
 
 
 TRACE_TERMS = ("Minv", "Minv2", "g5Minv", "MdagMinv", "dkappa", "dcsw", "dmu")

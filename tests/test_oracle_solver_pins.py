@@ -6,6 +6,10 @@ algebra, finite differences and closed forms on tiny lattices.
   - BiCGstab (solver list) on the non-Hermitian Mhat (mu != 0): dense solve of Mhat x = b;
   - block CG (solver list): dense solve for 3 right-hand sides, and with one right-hand side it is
     plain CG (same iterations, same iterate);
+  - block multishift CG (solver list): every shift's solution against the dense solve of
+    (Mhat^dag Mhat + sigma) X = B, with and without a zero shift; with one shift it is block CG (same
+    iterations, same iterate); with one column it takes the iterations of CG on the smallest shift;
+    planted mistakes in its shift recurrences (source mutations of the oracle function) fail the pins;
   - trace terms (section "Measurements", the abstract's reweighting traces): per noise equal to
     eta^dag A eta with the dense A; the dM/dp operators equal the derivative of the oracle's own
     M (central differences of dense M(p)), so Tr(M^-1 dM/dp) is the derivative of ln det M;
@@ -130,6 +134,72 @@ def test_block_cg_planted_mistake(tiny, monkeypatch):
     X, it = sv.block_cg(op, b, 1e-13, maxiter=60)
     monkeypatch.setattr(sv.np.linalg, "solve", real_solve)
     assert it == -1 or rel(_odd_vec(X[0], o), real_solve(A, _odd_vec(b[0], o))) > 1e-6
+
+
+# --- block multishift CG ------------------------------------------------------------------
+
+def _check_block_multishift(fn, op, o, Mhat, b, shifts):
+    A = Mhat.conj().T @ Mhat
+    Xs, it = fn(op, b, shifts, 1e-13)
+    if it <= 0:
+        return False
+    for X, s in zip(Xs, shifts):
+        for c in range(b.shape[0]):
+            want = np.linalg.solve(A + s * np.eye(len(o)), _odd_vec(b[c], o))
+            if rel(_odd_vec(X[c], o), want) > 1e-10:
+                return False
+    return True
+
+
+@pytest.mark.parametrize("shifts", [(0.0, 0.05, 0.7), (0.02, 0.3, 1.5, 4.0)])
+def test_block_multishift_dense(tiny, shifts):
+    dims, op, o, Mhat, b = tiny
+    assert _check_block_multishift(sv.block_multishift_cg, op, o, Mhat, b, shifts)
+
+
+def test_block_multishift_reduces_to_block_cg_and_cg(tiny):
+    dims, op, o, Mhat, b = tiny
+    Xs, it = sv.block_multishift_cg(op, b, (0.0,), 1e-12)
+    X, it2 = sv.block_cg(op, b, 1e-12)
+    assert it == it2 and rel(Xs[0], X) < 1e-12
+    # one column: the block recurrences are the scalar ones; the base (smallest shift) sets the count
+    Xs, it = sv.block_multishift_cg(op, b[:1], (0.1, 0.5), 1e-12)
+    x, it3 = sv.shifted_cg(op, b[0], 0.1, 1e-12)
+    assert it == it3 and rel(Xs[0][0], x) < 1e-10
+
+
+BMS_MUTATIONS = {
+    "beta of a shift with xi_k for xi_k-1": ("b_s = a_prev_s[s] @ inv(xi_prev[s]) @ C @ xi[s]",
+                                             "b_s = a_prev_s[s] @ inv(xi[s]) @ C @ xi[s]"),
+    "xi update multiplied on the wrong side": ("xi[s] = inv(a) @ xi[s] @ a_s", "xi[s] = a_s @ xi[s] @ inv(a)"),
+    "shift added to alpha instead of its inverse": ("a_s = inv(inv(a) + d * eye)", "a_s = a + d * eye"),
+    "shifted direction from the new residual": ("R = R - comb(Q, a)\n", "R -= comb(Q, a)\n"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BMS_MUTATIONS))
+def test_block_multishift_planted_mistakes(tiny, name):
+    import inspect
+    import textwrap
+    dims, op, o, Mhat, b = tiny
+    old, new = BMS_MUTATIONS[name]
+    src = textwrap.dedent(inspect.getsource(sv.block_multishift_cg))
+    assert src.count(old) == 1, old
+    if name == "shifted direction from the new residual":
+        # update R before the shifts read it (they need R_k, not R_k+1)
+        src = src.replace("        R = R - comb(Q, a)\n", "", 1)
+        src = src.replace("        a = np.linalg.solve(gram(P, Q), RR)\n",
+                          "        a = np.linalg.solve(gram(P, Q), RR)\n        R_old = R\n        R = R - comb(Q, a)\n", 1)
+    else:
+        src = src.replace(old, new, 1)
+    ns = dict(vars(sv))
+    exec(compile(src, "<mutant>", "exec"), ns)
+    mutant = ns["block_multishift_cg"]
+    try:
+        ok = _check_block_multishift(lambda *a: mutant(*a, maxiter=400), op, o, Mhat, b, (0.0, 0.05, 0.7))
+    except np.linalg.LinAlgError:
+        ok = False
+    assert not ok, name
 
 
 # --- trace terms ------------------------------------------------------------------------
