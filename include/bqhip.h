@@ -265,7 +265,14 @@ int bq_apply_noalloc(bq_op op, int kind, bq_field in, bq_field out, void* stream
  *                       operator step, per-column CG scalars on the device, FP32/FP16 inner
  *                       iterations with FP64 reliable updates when params->inner_prec asks for them;
  *   BQ_SOLVER_BICGSTAB  BiCGstab on Mhat (BQ_SYS_M, BQ_SYS_MHAT), FP64 or FP32 inner iterations;
- *   BQ_SOLVER_BLOCK_CG  block cg on Mhat^dag Mhat, FP64, nrhs <= 16.
+ *   BQ_SOLVER_BLOCK_CG  block CG on Mhat^dag Mhat (the block part of the list's "block multishift
+ *                       cg"), FP64, nrhs <= 16: all columns in one block Krylov space, with the
+ *                       N x N step matrices formed on the device.  A run ends when every column's
+ *                       recursive residual reaches tol; the FP64 residual is then recomputed and
+ *                       the columns that miss tol start a new run from it (at most 8 runs; counted
+ *                       in reliable_updates).  Columns that are numerically dependent at the start
+ *                       of a run (pivot below 1e-12 of their norm in a Cholesky pass) wait for the
+ *                       next run; a zero column gets x = 0.
  * b and x are FP64 fields with the subset of the system (BQ_SYS_NORMAL, BQ_SYS_MHAT: ODD,
  * otherwise FULL) and the same nrhs; x receives the solutions.  info points to nrhs entries
  * (may be NULL).  Returns BQ_ERR_NOT_CONVERGED if some column did not reach tol within maxiter
@@ -298,6 +305,12 @@ int bq_trace(bq_op op, uint64_t seed, int nnoise, int block, const bq_solve_para
  *   info       nshift*nrhs entries (may be NULL), info[k*nrhs + col]: a shift stops when its
  *              recursive residual |zeta_k r| <= tol |b|; true_rel_resid (= full_rel_resid) is
  *              |b - (A + shifts[k]) x[k]| / |b| recomputed in FP64 afterwards.
+ * params->solver = BQ_SOLVER_BLOCK_CG gives block multishift CG (the list's "block multishift cg";
+ * nrhs <= 16): the columns share one block Krylov space as well, and the block residual of each
+ * shift is R xi_k for the base residual block R and an nrhs x nrhs matrix xi_k per shift, whose
+ * recurrences follow from the three-term block relations of the base and shifted systems; a shift
+ * stops when |R xi_k e_col| <= tol |b_col| for all its columns.  There are no restarts: columns
+ * numerically dependent on others are not solved (their info reports BQ_ERR_NOT_CONVERGED).
  * Errors: BQ_ERR_INVALID, BQ_ERR_UNSUPPORTED (inner precision), BQ_ERR_NOT_CONVERGED (x holds the
  * last iterates), BQ_ERR_NONFINITE, BQ_ERR_OOM. */
 int bq_solve_multishift(bq_op op, bq_field b, int nshift, const double* shifts, bq_field* x,

@@ -334,12 +334,14 @@ class Op:
         a2 = np.frombuffer(t2, dtype=np.float64).copy()
         return a1[0::2] + 1j * a1[1::2], a2[0::2] + 1j * a2[1::2], [i.as_dict() for i in info]
 
-    def solve_multishift(self, b, xs, shifts, tol, maxiter=100000, chunk=8, stream=None, raise_on_error=True):
-        """(A + shifts[k]) xs[k] = b, A = Mhat^dag Mhat on odd sites; returns (rc, info[k][col])."""
+    def solve_multishift(self, b, xs, shifts, tol, maxiter=100000, chunk=8, stream=None, raise_on_error=True,
+                         solver=BQ_SOLVER_CG):
+        """(A + shifts[k]) xs[k] = b, A = Mhat^dag Mhat on odd sites; returns (rc, info[k][col]).
+        solver=BQ_SOLVER_BLOCK_CG: block multishift CG (all columns in one block Krylov space)."""
         n = len(shifts)
         if len(xs) != n:
             raise ValueError("one solution field per shift")
-        prm = bq_solve_params(float(tol), int(maxiter), BQ_F64, 0.0, BQ_SYS_NORMAL, int(chunk), 0)
+        prm = bq_solve_params(float(tol), int(maxiter), BQ_F64, 0.0, BQ_SYS_NORMAL, int(chunk), 0, int(solver))
         sh = (C.c_double * n)(*[float(v) for v in shifts])
         hx = (_h * n)(*[f.h for f in xs])
         info = (bq_solve_info * (n * b.nrhs))()

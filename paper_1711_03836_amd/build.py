@@ -33,7 +33,7 @@ FLAGS = [
 STENCIL_R = {0: (1, 2), 1: (1, 2, 3, 4), 2: (1, 2, 3, 4)}
 UNITS = [("bq_dslash_inst.hip", f"bq_dslash_p{p}_r{r}.o", [f"-DBQ_INST_PREC={p}", f"-DBQ_INST_R={r}"])
          for p, rs in STENCIL_R.items() for r in rs]
-UNITS += [(s, s.replace(".hip", ".o"), []) for s in ("bq_clover.hip", "bq_blas.hip", "bq_krylov.hip", "bq_api.hip")]
+UNITS += [(s, s.replace(".hip", ".o"), []) for s in ("bq_clover.hip", "bq_blas.hip", "bq_krylov.hip", "bq_block.hip", "bq_api.hip")]
 
 
 def _compile(unit, verbose: bool) -> str:

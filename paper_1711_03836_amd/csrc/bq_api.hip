@@ -918,6 +918,230 @@ static int cg_solve(bq_op op, Workspace* w, const bq_solve_params& prm, hipStrea
     return BQ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Block CG and block multishift CG (the solver list's "block multishift cg"): one block Krylov
+// space for all columns of b.  With shifts, the block residual of A + sigma_s is R xi_s for the
+// residual block R of the base system (base = the smallest shift), and a run ends when every
+// shift's every column has |R xi_s e_c| <= tol |b_c|.  With restarts (block CG of bq_solve) the
+// FP64 residual b - A x is then recomputed and the columns that miss tol start a new run from it;
+// columns found numerically dependent at the start of a run, and a run that breaks down, are
+// left to the next run the same way.
+// ---------------------------------------------------------------------------
+static const int kBlockRuns = 8;
+
+struct BlockOut {
+    std::vector<int> iters;   // per shift and column [s * ncol + c]: iterations while it iterated
+    std::vector<int> conv;    // per shift and column: recursive residual reached tol
+    std::vector<int> nrel;    // per column: runs after its first
+    std::vector<int> failed;  // per column: non-finite source
+    int breakdowns = 0;
+};
+
+static int block_engine(bq_op op, const Vec& B, int ncol, int nshift, const double* shifts, int base, const Vec* X,
+                        const bq_solve_params& prm, bool restarts, hipStream_t st, SolveAcct& acct, BlockOut& out)
+{
+    if (ncol < 1 || ncol > kBlockMax) return fail(BQ_ERR_UNSUPPORTED, "block CG takes 1..%d right-hand sides", kBlockMax);
+    if (nshift < 1 || nshift > kMaxShifts) return fail(BQ_ERR_INVALID, "nshift must be in 1..%d", kMaxShifts);
+    if (restarts && (nshift != 1 || shifts[0] != 0.0)) return fail(BQ_ERR_INVALID, "restarts need one zero shift");
+    bq_context ctx = op->gauge->ctx;
+    const Geom& g = op->gauge->g;
+    const double kap = op->kappa;
+    const int tiles = pad_sites(g.Vh) / kTile;
+    const int n = (int)B.half_sites;
+    const size_t units = B.half_units;
+    // work fields: residual, base direction, A P, Mhat P, even scratch, a direction per other shift
+    DevBuf d[5 + kMaxShifts], sc[5 + kMaxShifts];
+    Vec R, P, W, Q, T;
+    int nb_ = 0;
+    for (Vec* v : {&R, &P, &W, &Q, &T}) {
+        CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[nb_], sc[nb_], *v));
+        nb_++;
+    }
+    BlockFields f{};
+    for (int s = 0; s < nshift; s++) {
+        f.x[s] = X[s].all();
+        if (s == base) {
+            f.p[s] = P.all();
+            continue;
+        }
+        Vec v;
+        CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, d[nb_], sc[nb_], v));
+        nb_++;
+        f.p[s] = v.all();
+    }
+    // device state
+    const int nb = (ncol + 3) / 4;
+    const int ngroups = (tiles + kGramTiles - 1) / kGramTiles;
+    const size_t ns = (size_t)nshift * ncol;
+    DevBuf mats, dd, ii, part, rpart;
+    CHK(mats.alloc(ctx, sizeof(double2) * (size_t)kBlockMats * kBlockMax * kBlockMax));
+    CHK(dd.alloc(ctx, sizeof(double) * (size_t)ncol * 2));
+    CHK(ii.alloc(ctx, sizeof(int) * (BC_COUNT + ncol + 2 * ns)));
+    CHK(part.alloc(ctx, sizeof(double2) * (size_t)ngroups * nb * nb * 16));
+    CHK(rpart.alloc(ctx, sizeof(double) * (size_t)tiles * ncol));
+    BlockState S{};
+    S.mats = mats.as<double2>();
+    S.thr = dd.as<double>();
+    double* sums = S.thr + ncol;
+    S.ctrl = ii.as<int>();
+    S.colstat = S.ctrl + BC_COUNT;
+    S.sstat = S.colstat + ncol;
+    S.siters = S.sstat + ns;
+    S.ncol = ncol;
+    S.nshift = nshift;
+    S.base = base;
+    S.sigma_b = shifts[base];
+    for (int s = 0; s < nshift; s++) S.shift[s] = shifts[s] - shifts[base];
+    double2* pt = part.as<double2>();
+    double* rp = rpart.as<double>();
+    const double s64 = sp_bytes(PREC_F64), Vh = g.Vh;
+
+    // thresholds (tol |b_c|)^2; zero sources are solved by x = 0, non-finite ones fail
+    std::vector<double> b2(ncol), thr(ncol);
+    HIPCHK(launch_norm2(PREC_F64, B.all(), n, ncol, rp, tiles, st));
+    HIPCHK(launch_fin_sum(rp, tiles, ncol, sums, st));
+    HIPCHK(hipMemcpyAsync(b2.data(), sums, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int> cs(ncol), ss(ns, 0), si(ns, 0);
+    out.iters.assign(ns, 0);
+    out.conv.assign(ns, 0);
+    out.nrel.assign(ncol, 0);
+    out.failed.assign(ncol, 0);
+    for (int c = 0; c < ncol; c++) {
+        thr[c] = prm.tol * prm.tol * b2[c];
+        if (!std::isfinite(b2[c])) {
+            cs[c] = COL_FAILED;
+            out.failed[c] = 1;
+        } else if (b2[c] == 0.0) {
+            cs[c] = COL_DONE;
+            for (int s = 0; s < nshift; s++) ss[(size_t)s * ncol + c] = out.conv[(size_t)s * ncol + c] = 1;
+        } else {
+            cs[c] = COL_ACTIVE;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(S.thr, thr.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(S.sstat, ss.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(S.siters, si.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st));
+    for (int s = 0; s < nshift; s++) HIPCHK(launch_zero(PREC_F64, f.x[s], n, ncol, nullptr, 0, st));
+    HIPCHK(launch_convert(PREC_F64, B.all(), PREC_F64, R.all(), n, ncol, nullptr, 0, st));
+    acct.bytes += ncol * Vh * s64 * (1 + nshift + 2);
+    acct.launches += 3 + nshift;
+
+    OpCall c{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, S.colstat, 1 << COL_ACTIVE, st};
+    OpCall c64{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, nullptr, 1, st};
+    const int kchunk = prm.chunk > 0 ? prm.chunk : 8;
+    const long maxiter = prm.maxiter > 0 ? prm.maxiter : 100000;
+    const int per_iter = 13 + (nshift > 1);
+    long total = 0;
+    int runs = 0;
+    std::vector<int> ctrl(BC_COUNT);
+    while (true) {
+        unsigned cand = 0;
+        for (int c2 = 0; c2 < ncol; c2++)
+            if (cs[c2] == COL_ACTIVE) cand |= 1u << c2;
+        if (!cand) break;
+        // a run: the candidates' Gram matrix, then the device picks the independent columns
+        std::vector<int> c0(BC_COUNT, 0);
+        c0[BC_MASK] = (int)cand;
+        HIPCHK(hipMemcpyAsync(S.ctrl, c0.data(), sizeof(int) * BC_COUNT, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(S.colstat, cs.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_convert(PREC_F64, R.all(), PREC_F64, P.all(), n, ncol, nullptr, 0, st));
+        for (int s = 0; s < nshift; s++)
+            if (s != base) HIPCHK(launch_convert(PREC_F64, R.all(), PREC_F64, f.p[s], n, ncol, nullptr, 0, st));
+        HIPCHK(launch_block_gram(R.all(), R.all(), FieldArg(), 0.0, S, g.Vh, tiles, pt, st));
+        HIPCHK(launch_block_gram_fin(S, pt, tiles, BM_RR, st));
+        HIPCHK(launch_block_step(S, 0, st));
+        runs++;
+        long run_iters = 0;
+        while (true) {
+            for (int it = 0; it < kchunk; it++) {
+                CHK(k1(c, 0, P.all(), T.all()));
+                CHK(tv(c, 0, 1, T.all(), P.all(), Q.all(), -kap * kap, nullptr, tiles, tiles));
+                CHK(k1(c, 1, Q.all(), T.all()));
+                CHK(tv(c, 1, 1, T.all(), Q.all(), W.all(), -kap * kap, nullptr, tiles, tiles));
+                HIPCHK(launch_block_gram(P.all(), W.all(), P.all(), S.sigma_b, S, g.Vh, tiles, pt, st));
+                HIPCHK(launch_block_gram_fin(S, pt, tiles, BM_PQ, st));
+                HIPCHK(launch_block_step(S, 1, st));
+                if (nshift > 1) HIPCHK(launch_block_shift(S, f, R.all(), units, st));
+                HIPCHK(launch_block_xr(S, f.x[base], P.all(), W.all(), R.all(), units, st));
+                HIPCHK(launch_block_gram(R.all(), R.all(), FieldArg(), 0.0, S, g.Vh, tiles, pt, st));
+                HIPCHK(launch_block_gram_fin(S, pt, tiles, BM_RRN, st));
+                HIPCHK(launch_block_step(S, 2, st));
+                HIPCHK(launch_block_p(S, P.all(), R.all(), units, st));
+            }
+            acct.launches += (long long)kchunk * per_iter;
+            acct.chunks++;
+            HIPCHK(hipMemcpyAsync(ctrl.data(), S.ctrl, sizeof(int) * BC_COUNT, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            run_iters = ctrl[BC_K];
+            if (ctrl[BC_STOP] || total + run_iters >= maxiter) break;
+        }
+        // bookkeeping of the run
+        HIPCHK(hipMemcpyAsync(ss.data(), S.sstat, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(si.data(), S.siters, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const unsigned amask = (unsigned)ctrl[BC_MASK];
+        const int na = ctrl[BC_NA];
+        total += run_iters;
+        acct.iterations += (int)run_iters;
+        if (ctrl[BC_BREAK]) out.breakdowns++;
+        double shift_cols = 0;
+        for (int c2 = 0; c2 < ncol; c2++) {
+            if (!((amask >> c2) & 1u)) continue;
+            for (int s = 0; s < nshift; s++) {
+                const size_t e = (size_t)s * ncol + c2;
+                const int it = ss[e] ? si[e] : (int)run_iters;
+                out.iters[e] += it;
+                out.conv[e] = ss[e];
+                if (s != base) shift_cols += it;
+            }
+        }
+        // stencils, Gram matrices and column combinations per active column; per shift its direction
+        // and solution; links and clover of the four stencil launches once per iteration
+        acct.bytes += run_iters * (iter_shared_bytes(op, PREC_F64) + na * Vh * s64 * 22.0) + shift_cols * Vh * s64 * 5;
+        acct.bytes += ncol * Vh * s64 * (2 + (nshift - 1) * 2 + 1);
+        if (!restarts) break;
+        // FP64 residual b - A x for every column
+        CHK(op_fwd(c64, 0, X[base], Q, T, nullptr, tiles));
+        CHK(op_dag_r(c64, 0, Q, T, B, R, nullptr, rp, tiles));
+        HIPCHK(launch_fin_sum(rp, tiles, ncol, sums, st));
+        std::vector<double> r2(ncol);
+        HIPCHK(hipMemcpyAsync(r2.data(), sums, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        acct.bytes += iter_shared_bytes(op, PREC_F64) + ncol * Vh * s64 * 11;
+        acct.launches += 5;
+        bool more = false;
+        for (int c2 = 0; c2 < ncol; c2++) {
+            if (cs[c2] != COL_ACTIVE) continue;
+            if (r2[c2] <= thr[c2]) {
+                cs[c2] = COL_DONE;
+                out.conv[c2] = 1;
+            } else {
+                out.conv[c2] = 0;
+                more = true;
+            }
+        }
+        if (!more || total >= maxiter || runs >= kBlockRuns) break;
+        for (int c2 = 0; c2 < ncol; c2++)
+            if (cs[c2] == COL_ACTIVE) out.nrel[c2]++;
+    }
+    return BQ_OK;
+}
+
+static int bcg_solve(bq_op op, Workspace* w, const bq_solve_params& prm, hipStream_t st, std::vector<int>& iters,
+                     std::vector<int>& nrel, std::vector<int>& status, SolveAcct& acct)
+{
+    const double zero = 0.0;
+    BlockOut o;
+    CHK(block_engine(op, w->bp, w->ncol, 1, &zero, 0, &w->x, prm, true, st, acct, o));
+    iters = o.iters;
+    nrel = o.nrel;
+    status.assign(w->ncol, COL_DONE);
+    for (int c = 0; c < w->ncol; c++)
+        if (o.failed[c]) status[c] = COL_FAILED;
+    return BQ_OK;
+}
+
 // |v|^2 per column into host vector
 static int norms(bq_op op, Workspace* w, const Vec& v, int ncol, std::vector<double>& out, hipStream_t st)
 {
@@ -977,7 +1201,10 @@ static int solve_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec&
     }
 
     std::vector<int> iters, nrel, status;
-    CHK(cg_solve(op, w, prm, st, iters, nrel, status, acct));
+    if (prm.solver == BQ_SOLVER_BLOCK_CG)
+        CHK(bcg_solve(op, w, prm, st, iters, nrel, status, acct));
+    else
+        CHK(cg_solve(op, w, prm, st, iters, nrel, status, acct));
 
     // final FP64 true residual of the CG system for every column
     {
@@ -1244,14 +1471,6 @@ static int bicg_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec& 
     if (rc == BQ_ERR_NOT_CONVERGED) fail(rc, "some right-hand side did not converge within maxiter");
     if (rc == BQ_ERR_NONFINITE) fail(rc, "non-finite value in the source or during the solve");
     return rc;
-}
-
-static int bcg_views(bq_op op, const Vec& b_even, const Vec& b_odd, const Vec& x_even, const Vec& x_odd, int ncol,
-                     const bq_solve_params& prm, bq_solve_info* info, hipStream_t st, SolveAcct& acct)
-{
-    (void)op; (void)b_even; (void)b_odd; (void)x_even; (void)x_odd; (void)ncol; (void)prm; (void)info; (void)st;
-    (void)acct;
-    return fail(BQ_ERR_UNSUPPORTED, "block CG is not available in this build");
 }
 
 // ---------------------------------------------------------------------------
@@ -1849,6 +2068,8 @@ static int check_solve_params(const bq_solve_params& p)
     }
     if (p.solver == BQ_SOLVER_BLOCK_CG && p.inner_prec != BQ_F64)
         return fail(BQ_ERR_UNSUPPORTED, "block CG iterates in FP64");
+    if (p.solver == BQ_SOLVER_BLOCK_CG && p.system == BQ_SYS_FULL_NORMAL)
+        return fail(BQ_ERR_UNSUPPORTED, "block CG solves the even-odd systems");
     if (p.solver != BQ_SOLVER_CG && p.use_graph) return fail(BQ_ERR_UNSUPPORTED, "graph capture is for CG only");
     if (p.maxiter < 0 || p.chunk < 0 || !(p.delta >= 0) || !(p.delta < 1))
         return fail(BQ_ERR_INVALID, "maxiter and chunk must be >= 0 and delta in [0, 1)");
@@ -1865,6 +2086,8 @@ int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq
     if (b->prec != BQ_F64 || x->prec != BQ_F64) return fail(BQ_ERR_INVALID, "b and x must be FP64 fields");
     if (b->nrhs != x->nrhs) return fail(BQ_ERR_INVALID, "b and x have different nrhs");
     if (b == x) return fail(BQ_ERR_INVALID, "b and x must be different fields");
+    if (p.solver == BQ_SOLVER_BLOCK_CG && b->nrhs > kBlockMax)
+        return fail(BQ_ERR_UNSUPPORTED, "block CG takes at most %d right-hand sides", kBlockMax);
     for (int k = 0; k < 4; k++)
         if (b->dims[k] != op->gauge->dims[k] || x->dims[k] != op->gauge->dims[k])
             return fail(BQ_ERR_INVALID, "field and gauge lattices differ");
@@ -1889,9 +2112,7 @@ int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq
     int rc;
     if (p.solver == BQ_SOLVER_BICGSTAB)
         rc = bicg_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
-    else if (p.solver == BQ_SOLVER_BLOCK_CG)
-        rc = bcg_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
-    else
+    else  // CG and block CG share the system preparation, the residuals and the reconstruction
         rc = solve_views(op, be, bo, xe, xo, b->nrhs, p, info, ctx->stream, acct);
     HIPCHK(hipEventRecord(e1, ctx->stream));
     HIPCHK(hipEventSynchronize(e1));
@@ -1905,6 +2126,87 @@ int bq_solve(bq_op op, bq_field b, bq_field x, const bq_solve_params* params, bq
     op->last.chunks = acct.chunks;
     op->last.iterations = acct.iterations;
     return rc;
+}
+
+// Block multishift CG: every column of b and every shift in one block Krylov space; per shift
+// and column the FP64 residual |b - (Mhat^dag Mhat + sigma) x| is recomputed at the end.
+static int ms_block(bq_op op, bq_field b, int nshift, const double* shifts, int base, bq_field* x,
+                    const bq_solve_params& prm, bq_solve_info* info, hipStream_t st)
+{
+    bq_context ctx = op->gauge->ctx;
+    const Geom& g = op->gauge->g;
+    const int ncol = b->nrhs;
+    if (ncol > kBlockMax) return fail(BQ_ERR_UNSUPPORTED, "block CG takes at most %d right-hand sides", kBlockMax);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    SolveAcct acct;
+    const Vec bv = parity_vec(b, 1);
+    std::vector<Vec> xv(nshift);
+    for (int k = 0; k < nshift; k++) xv[k] = parity_vec(x[k], 1);
+    BlockOut o;
+    CHK(block_engine(op, bv, ncol, nshift, shifts, base, xv.data(), prm, false, st, acct, o));
+    // FP64 residuals per shift
+    DevBuf dq, sq, dt, stt, dw, sw, part, sum;
+    Vec q, t, w;
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dq, sq, q));
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dt, stt, t));
+    CHK(alloc_vec(ctx, g, PREC_F64, 1, ncol, dw, sw, w));
+    const int hw = pad_sites(g.Vh) / kTile;
+    const int n = (int)bv.half_sites;
+    CHK(part.alloc(ctx, sizeof(double) * (size_t)hw * ncol));
+    CHK(sum.alloc(ctx, sizeof(double) * (size_t)ncol));
+    double* pr = part.as<double>();
+    OpCall c64{op, PREC_F64, get_tune(ctx, PREC_F64, ncol), ncol, nullptr, 1, st};
+    std::vector<double> b2(ncol), r2((size_t)nshift * ncol);
+    HIPCHK(launch_norm2(PREC_F64, bv.all(), n, ncol, pr, hw, st));
+    HIPCHK(launch_fin_sum(pr, hw, ncol, sum.as<double>(), st));
+    HIPCHK(hipMemcpyAsync(b2.data(), sum.p, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+    for (int k = 0; k < nshift; k++) {
+        CHK(op_fwd(c64, 0, xv[k], q, t, nullptr, hw));
+        CHK(op_dag_r(c64, 0, q, t, bv, w, nullptr, nullptr, hw));
+        HIPCHK(launch_axpy_norm(xv[k].all(), w.all(), -shifts[k], n, ncol, pr, hw, st));
+        HIPCHK(launch_fin_sum(pr, hw, ncol, sum.as<double>(), st));
+        HIPCHK(hipMemcpyAsync(r2.data() + (size_t)k * ncol, sum.p, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    acct.bytes += nshift * (iter_shared_bytes(op, PREC_F64) + ncol * g.Vh * sp_bytes(PREC_F64) * 13);
+    acct.launches += 8L * nshift;
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    op->last.bytes = acct.bytes;
+    op->last.seconds = ms * 1e-3;
+    op->last.launches = acct.launches;
+    op->last.chunks = acct.chunks;
+    op->last.iterations = acct.iterations;
+    int rc = BQ_OK;
+    for (int k = 0; k < nshift; k++)
+        for (int cc = 0; cc < ncol; cc++) {
+            const size_t e = (size_t)k * ncol + cc;
+            const double tr = b2[cc] > 0 ? std::sqrt(r2[e] / b2[cc]) : 0.0;
+            int cst = BQ_OK;
+            if (o.failed[cc] || !std::isfinite(tr)) cst = BQ_ERR_NONFINITE;
+            else if (!o.conv[e]) cst = BQ_ERR_NOT_CONVERGED;
+            if (info) {
+                bq_solve_info& in = info[e];
+                in.iters = o.iters[e];
+                in.reliable_updates = 0;
+                in.true_rel_resid = tr;
+                in.full_rel_resid = tr;
+                in.converged = cst == BQ_OK;
+                in.status = cst;
+            }
+            if (cst == BQ_ERR_NONFINITE) rc = cst;
+            else if (cst != BQ_OK && rc == BQ_OK) rc = cst;
+        }
+    if (rc == BQ_ERR_NOT_CONVERGED) return fail(rc, "some shift did not converge within maxiter");
+    if (rc == BQ_ERR_NONFINITE) return fail(rc, "non-finite value in the source or during the solve");
+    return BQ_OK;
 }
 
 // Multishift CG (the solver list's "multishift cg", the RHMC solver): all shifts share the Krylov
@@ -1941,6 +2243,7 @@ int bq_solve_multishift(bq_op op, bq_field b, int nshift, const double* shifts, 
     HIPCHK(hipSetDevice(ctx->device));
     CHK(sync_with(ctx, (hipStream_t)stream));
     hipStream_t st = ctx->stream;
+    if (prm.solver == BQ_SOLVER_BLOCK_CG) return ms_block(op, b, nshift, shifts, base, x, prm, info, st);
     const Geom& g = op->gauge->g;
     const int ncol = b->nrhs;
     const double sb = shifts[base], kap = op->kappa;

@@ -162,6 +162,61 @@ hipError_t launch_ms_update2(const MsState& s, const MsFields& f, int n, int nco
                              hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// block (multishift) CG: one block Krylov space for N <= kBlockMax columns; the N x N step
+// matrices live on the device and are computed there by one wavefront, so a run needs no host
+// round trip per iteration
+// ---------------------------------------------------------------------------
+constexpr int kBlockMax = 16;   // columns of a block solve
+constexpr int kGramTiles = 8;   // 64-site tiles one wavefront sums before it writes its partial
+// control words
+enum { BC_K = 0, BC_STOP = 1, BC_BREAK = 2, BC_NA = 3, BC_MASK = 4, BC_IDX = 5,
+       BC_FROZEN = BC_IDX + kBlockMax, BC_COUNT = BC_FROZEN + kMaxShifts };
+// matrix slots (kBlockMax x kBlockMax complex each, row-major).  "Full" matrices are indexed by
+// column number and vanish outside the active columns; "packed" ones hold the na x na block of the
+// active columns in the order of the active list.
+enum { BM_PQ = 0,       // full: P^dag (A P + sigma_b P)
+       BM_RR = 1,       // full: R^dag R of the current residual block
+       BM_RRN = 2,      // full: R^dag R of the new residual block
+       BM_ALPHA = 3,    // full: base step matrix alpha_k
+       BM_BETA = 4,     // full: base direction matrix beta_k
+       BM_AINV = 5,     // packed: alpha_k^-1
+       BM_C = 6,        // packed: alpha_k^-1 beta_k
+       BM_SHIFT = 7 };  // per shift s at BM_SHIFT + 6 s: packed xi_k, packed xi_k-1, packed alpha^s_k-1,
+                        // full xi_k (for the direction update), full alpha^s_k, full beta^s_k-1
+constexpr int kBlockMats = BM_SHIFT + 6 * kMaxShifts;
+struct BlockState {
+    double2* mats;   // kBlockMats matrices
+    double* thr;     // per column: (tol |b_c|)^2
+    int* ctrl;       // BC_* words
+    int* colstat;    // per column: COL_ACTIVE while in the block, COL_DONE otherwise (stencil filter)
+    int* sstat;      // per shift and column [s * ncol + c]: 0 iterating, 1 converged
+    int* siters;     // per shift and column: iteration at which it converged
+    int ncol, nshift, base;
+    double sigma_b;                // shift of the base system (added to A P)
+    double shift[kMaxShifts];      // sigma_s - sigma_b
+};
+struct BlockFields {
+    FieldArg x[kMaxShifts];        // solutions (x[base] is the base iterate)
+    FieldArg p[kMaxShifts];        // directions (p[base] is the base direction)
+};
+// partial Gram sums of <X_i, Y_j + s Z_j> over the active columns (Z may be null); one set of
+// kBlockMax^2 complex numbers per group of kGramTiles tiles
+hipError_t launch_block_gram(FieldArg X, FieldArg Y, FieldArg Z, double s, const BlockState& S, int vh, int tiles,
+                             double2* partial, hipStream_t st);
+// fixed-order sum of the partials into matrix slot `slot` (full)
+hipError_t launch_block_gram_fin(const BlockState& S, const double2* partial, int tiles, int slot, hipStream_t st);
+// 0: start of a run (active list from colstat and the Gram matrix in BM_RR, dependent columns
+// dropped); 1: alpha and the shift recurrences (after BM_PQ); 2: convergence, beta (after BM_RRN)
+hipError_t launch_block_step(const BlockState& S, int phase, hipStream_t st);
+// x_base += P alpha, R -= (W + sigma_b P) alpha
+hipError_t launch_block_xr(const BlockState& S, FieldArg x, FieldArg p, FieldArg w, FieldArg r, size_t units,
+                           hipStream_t st);
+// P = R + P beta
+hipError_t launch_block_p(const BlockState& S, FieldArg p, FieldArg r, size_t units, hipStream_t st);
+// every shift s other than the base: p_s = R xi + p_s beta_s, x_s += p_s alpha_s
+hipError_t launch_block_shift(const BlockState& S, const BlockFields& f, FieldArg r, size_t units, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // BiCGstab on Mhat (inner precision FP64 or FP32, FP64 reductions, FP64 restarts)
 // ---------------------------------------------------------------------------
 struct BicgScalars {
