@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=4)
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--other-inner", type=int, default=1, help="also time the other inner precision (1/0)")
+    ap.add_argument("--block", type=int, default=1, help="also time FP64 block CG on the same sources (1/0)")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests of the short serving run (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8)
     args = ap.parse_args()
@@ -135,6 +136,22 @@ def main():
         log(f"[bench] FP64 CG {mixed_vs['fp64_ms']:.1f} ms vs mixed {mixed_vs['mixed_ms']:.1f} ms "
             f"(x{mixed_vs['speedup']:.2f})")
 
+    # block CG (FP64): the 12 columns in one block Krylov space, same sources and tolerance
+    block = None
+    if not args.no_fp64 and args.block:
+        rc_b, info_b = op.solve(fb, fx, tol, system=bq.BQ_SYS_M, inner_prec=0, solver=bq.BQ_SOLVER_BLOCK_CG)
+        st_b = op.stats()
+        assert all(c["converged"] for c in info_b), info_b
+        block = {"ms": st_b["seconds"] * 1e3, "iters": max(c["iters"] for c in info_b),
+                 "runs_after_first": max(c["reliable_updates"] for c in info_b),
+                 "speedup_vs_fp64_cg": st64["seconds"] / st_b["seconds"],
+                 "iters_vs_fp64_cg": max(c["iters"] for c in info_b) / max(c["iters"] for c in info64),
+                 "gbs": st_b["bytes"] / st_b["seconds"] / 1e9,
+                 "true_rel_resid": max(c["true_rel_resid"] for c in info_b),
+                 "full_rel_resid": max(c["full_rel_resid"] for c in info_b)}
+        log(f"[bench] FP64 block CG {block['ms']:.1f} ms, {block['iters']} iterations "
+            f"(FP64 CG {mixed_vs['fp64_ms']:.1f} ms, {mixed_vs['fp64_iters']} iterations)")
+
     # the other inner precision on the same sources (FP16 storage with FP32 arithmetic, or FP32)
     other = None
     if not args.no_fp64 and args.other_inner:
@@ -190,7 +207,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(dims, U, kappa, csw, mu, b, op, inner)
+        cpu = cpu_baseline(dims, U, kappa, csw, mu, b, op, inner,
+                           gpu_iters=mixed_vs["fp64_iters"] if mixed_vs else None)
 
     out = {
         "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -200,7 +218,11 @@ def main():
                                f"mu={mu}, kappa={kappa}, c_SW={csw}, U=exp({eps} i H), tol {tol:g}, "
                                f"{args.inner} inner + f64 reliable updates",
                    "lattice": list(dims), "nrhs": nrhs, "plaquette": plaq},
-        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "other_inner": other, "dslash": dslash,
+        "value_is": "solve-level rate of the timed mixed-precision CG solves: algorithmic HBM bytes (every "
+                    "kernel's inputs read once and outputs written once) per wall-clock second; the Dslash "
+                    "kernel's own rate is roofline.achieved",
+        "roofline": roof, "cpu_baseline": cpu, "mixed_vs_fp64": mixed_vs, "block_cg": block, "other_inner": other,
+        "dslash": dslash,
         "dslash_single_rhs": single, "serving": serving,
         "solve": {"true_rel_resid": worst_true, "full_rel_resid": worst_full,
                   "iters": max(c["iters"] for c in last_info),
@@ -277,10 +299,13 @@ def serve(bq, ctx, nreq, load):
             "mix": "lattices {8^4, 16^3x32, 24^3x48, 32^3x64}, kappa U[0.118,0.124], c_SW 1.5, 1-12 RHS, tol 1e-10"}
 
 
-def cpu_baseline(dims, U, kappa, csw, mu, b, op, inner):
+def cpu_baseline(dims, U, kappa, csw, mu, b, op, inner, gpu_iters=None):
     """The CPU oracle on a bounded sample of the same workload: two CG iterations on Mhat^dag Mhat for one
-    point source on the full lattice, scaled to GB/s with the same algorithmic byte count as the GPU."""
+    point source on the full lattice, scaled to GB/s with the same algorithmic byte count as the GPU (the
+    oracle works on full-lattice arrays, so its own traffic is larger), and the time-to-solution of the 12
+    sources extrapolated from the GPU's FP64 CG iteration count."""
     from oracle import oracle as orc
+    from oracle.baseline_times import cpu_model
     log("[bench] CPU oracle: building clover field and inverse ...")
     t0 = time.time()
     ref = orc.Operator(dims, U, kappa, csw, mu=mu)
@@ -295,10 +320,15 @@ def cpu_baseline(dims, U, kappa, csw, mu, b, op, inner):
     # per output site) + spinor traffic + vector updates, the same model the GPU library uses
     s64 = 24 * 8
     per_iter = 4 * Vh * (8 * 18 * 8 + 72 * 8) + Vh * (2 + 3 + 2 + 4) * s64 + Vh * 5 * s64
-    return {"value": iters * per_iter / dt / 1e9, "unit": "GB/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{iters} FP64 CG iterations on Mhat^dag Mhat, 1 of the 12 point sources, full "
-                      f"{'x'.join(map(str, dims))} lattice ({dt:.1f}s)",
-            "seconds_per_iteration": dt / iters}
+    out = {"value": iters * per_iter / dt / 1e9, "unit": "GB/s", "cores": orc.num_threads(), "kind": "oracle",
+           "sample": f"{iters} FP64 CG iterations on Mhat^dag Mhat, 1 of the 12 point sources, full "
+                     f"{'x'.join(map(str, dims))} lattice ({dt:.1f}s)",
+           "seconds_per_iteration": dt / iters, "cpu_model": cpu_model()}
+    if gpu_iters:
+        out["extrapolated_time_to_solution_s"] = dt / iters * gpu_iters * b.shape[0]
+        out["extrapolation"] = (f"seconds per iteration x {gpu_iters} iterations (the GPU FP64 CG count) x "
+                                f"{b.shape[0]} sources")
+    return out
 
 
 if __name__ == "__main__":

@@ -162,67 +162,40 @@ __device__ __forceinline__ uint32_t f2h(float f) { return (uint32_t)__half_as_us
 
 // Streaming accesses: links and clover are read once per launch and outputs written once;
 // non-temporal loads/stores keep them from evicting the neighbour spinors that the stencil
-// re-reads from L2.  BQ_STREAMING_HINTS=0 turns the hints off.
-#ifndef BQ_STREAMING_HINTS
-#define BQ_STREAMING_HINTS 1
-#endif
+// re-reads from L2.
 typedef double bq_d2v __attribute__((ext_vector_type(2)));
 typedef float bq_f2v __attribute__((ext_vector_type(2)));
 typedef unsigned bq_u2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double2 ld_stream(const double2* p)
 {
-#if BQ_STREAMING_HINTS
     const bq_d2v t = __builtin_nontemporal_load((const bq_d2v*)p);
     return make_double2(t.x, t.y);
-#else
-    return *p;
-#endif
 }
 __device__ __forceinline__ float2 ld_stream(const float2* p)
 {
-#if BQ_STREAMING_HINTS
     const bq_f2v t = __builtin_nontemporal_load((const bq_f2v*)p);
     return make_float2(t.x, t.y);
-#else
-    return *p;
-#endif
 }
 __device__ __forceinline__ uint2 ld_stream(const uint2* p)
 {
-#if BQ_STREAMING_HINTS
     const bq_u2v t = __builtin_nontemporal_load((const bq_u2v*)p);
     return make_uint2(t.x, t.y);
-#else
-    return *p;
-#endif
 }
 __device__ __forceinline__ void st_stream(double2* p, double2 v)
 {
-#if BQ_STREAMING_HINTS
     bq_d2v t = {v.x, v.y};
     __builtin_nontemporal_store(t, (bq_d2v*)p);
-#else
-    *p = v;
-#endif
 }
 __device__ __forceinline__ void st_stream(float2* p, float2 v)
 {
-#if BQ_STREAMING_HINTS
     bq_f2v t = {v.x, v.y};
     __builtin_nontemporal_store(t, (bq_f2v*)p);
-#else
-    *p = v;
-#endif
 }
 __device__ __forceinline__ void st_stream(uint2* p, uint2 v)
 {
-#if BQ_STREAMING_HINTS
     bq_u2v t = {v.x, v.y};
     __builtin_nontemporal_store(t, (bq_u2v*)p);
-#else
-    *p = v;
-#endif
 }
 
 template <class P, int N> struct CxIO;

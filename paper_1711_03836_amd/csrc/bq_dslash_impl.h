@@ -15,10 +15,6 @@
 
 #include "bq_kernels.h"
 
-#ifndef BQ_BUFFER_LOADS
-#define BQ_BUFFER_LOADS 1
-#endif
-
 namespace bq {
 namespace dslash {
 
@@ -247,7 +243,6 @@ template <class P, int LA>
 __device__ __forceinline__ void load_clover_block(const typename P::unit* __restrict__ C, int j, int blk,
                                                   cx<typename P::real> (&c)[18])
 {
-#if BQ_BUFFER_LOADS
     using U = typename P::unit;
     constexpr int NU = 36 / P::cpu;  // units of both blocks
     // The resource starts at the wave's own tile (j's tile is uniform over the wave), so offsets
@@ -294,18 +289,6 @@ __device__ __forceinline__ void load_clover_block(const typename P::unit* __rest
 #pragma unroll
         for (int k = 0; k < 9; k++) CxIO<P16, 2>::unpack(u[k], c[2 * k], c[2 * k + 1]);
     }
-#else
-    if constexpr (P::id == PREC_F16) {
-#pragma unroll
-        for (int u = 0; u < 9; u++) CxIO<P16, 2>::unpack(ld_stream(&at(C, j, blk * 9 + u, 18)), c[2 * u], c[2 * u + 1]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 18; k++) {
-            auto t = ld_stream(&at(C, j, blk * 18 + k, 36));
-            c[k] = {t.x, t.y};
-        }
-    }
-#endif
 }
 
 // the same block from a tile's clover copy in LDS, laid out [unit][lane]
@@ -429,16 +412,8 @@ struct HalfHop {
 template <class P, class PR, int R, int RECON>
 __device__ __forceinline__ void hh_load_spinor(const Args<P, PR>& A, int c, int r, HalfHop<P, R, RECON>& d)
 {
-#if BQ_BUFFER_LOADS
     load_units<P, 12, 0>(buf_rsrc(A.in.d + c * A.in.cstride), d.jn, d.sp[r]);
     if constexpr (P::id == PREC_F16) d.sc[r] = buf_load4f(buf_rsrc(A.in.s + c * A.in.sstride), (uint32_t)d.jn * 4u);
-#else
-    constexpr int SU = 12 / P::cpu;
-    const typename P::unit* __restrict__ b = A.in.d + c * A.in.cstride;
-#pragma unroll
-    for (int k = 0; k < SU; k++) d.sp[r].u[k] = at(b, d.jn, k, SU);
-    if constexpr (P::id == PREC_F16) d.sc[r] = A.in.s[c * A.in.sstride + d.jn];
-#endif
 }
 
 // neighbour index and link of half hop H: forward U_mu(x) stored at x, backward U_mu(x - mu)
@@ -448,16 +423,10 @@ __device__ __forceinline__ void hh_load_link(const Args<P, PR>& A, const Site& s
 {
     constexpr int MU = H >> 1;
     constexpr bool BW = H & 1;
-    constexpr int LU = link_cx<RECON>() / P::cpu;
     d.jn = nbr(A.g, s, MU, BW ? -1 : +1);
     const typename P::unit* __restrict__ U = A.U[(BW ? 1 - A.parity : A.parity) * 4 + MU];
     const int jl = BW ? d.jn : s.j;
-#if BQ_BUFFER_LOADS
     load_units<P, link_cx<RECON>(), LA>(buf_rsrc(U), jl, d.link);
-#else
-#pragma unroll
-    for (int k = 0; k < LU; k++) d.link.u[k] = ld_stream(&at(U, jl, k, LU));
-#endif
 }
 
 template <class P, class PR, int R, int RECON, int H, int LA>
@@ -506,13 +475,10 @@ __device__ __forceinline__ void hh_compute(const Args<P, PR>& A, const Site& s, 
 
 // Loading one half hop ahead doubles the raw data held in registers; it is used where the
 // two buffers fit without spilling (one FP64 column, up to two FP32, up to three FP16).
-#ifndef BQ_PREFETCH
-#define BQ_PREFETCH 1
-#endif
 template <class P, int R>
 constexpr bool prefetch_hops()
 {
-    return BQ_PREFETCH && (P::id == PREC_F64 ? R <= 1 : (P::id == PREC_F32 ? R <= 2 : R <= 3));
+    return P::id == PREC_F64 ? R <= 1 : (P::id == PREC_F32 ? R <= 2 : R <= 3);
 }
 
 template <class P, class PR, int R, int DAG, int RECON, int H, bool PF, int LA>

@@ -84,6 +84,7 @@ def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_pre
         arrivals = np.zeros(len(reqs))
     t0 = time.perf_counter()
     nxt, pending, lat, info_worst, ncols = 0, {}, [], 0.0, 0
+    by_dims = {}
     done_count = 0
     while done_count < len(reqs):
         now = time.perf_counter() - t0
@@ -104,6 +105,7 @@ def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_pre
             if rc != bq.BQ_OK:
                 raise RuntimeError(f"request {i} failed: {rc} {info}")
             lat.append(tdone - tarr)
+            by_dims.setdefault(reqs[i]["dims"], []).append((tdone - tarr, len(info)))
             info_worst = max(info_worst, max(c["true_rel_resid"] for c in info))
             ncols += len(info)
             done_count += 1
@@ -111,9 +113,15 @@ def run(bq, world, server, reqs, qps=None, seed=0, csw=1.5, tol=1e-10, inner_pre
                 log(f"[serve] {done_count}/{len(reqs)} done, p50 so far {np.percentile(lat, 50):.3f}s")
     span = time.perf_counter() - t0
     lat = np.array(lat)
+    per = {}
+    for d, v in sorted(by_dims.items()):
+        lv = np.array([a for a, _ in v])
+        per["x".join(map(str, d))] = {"requests": len(v), "rhs": int(sum(n for _, n in v)),
+                                      "p50_s": float(np.percentile(lv, 50)), "p99_s": float(np.percentile(lv, 99)),
+                                      "mean_s": float(lv.mean())}
     return {"requests": len(reqs), "rhs": ncols, "seconds": span, "solves_per_s": len(reqs) / span,
             "rhs_per_s": ncols / span, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "qps": qps, "worst_true_rel_resid": info_worst}
+            "mean_s": float(lat.mean()), "qps": qps, "worst_true_rel_resid": info_worst, "per_lattice": per}
 
 
 def main():
@@ -127,6 +135,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--inner", choices=["f64", "f32", "f16"], default="f32")
     ap.add_argument("--seed", type=int, default=2017)
+    ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     args = ap.parse_args()
 
     from paper_1711_03836_amd import bqhip as bq
@@ -154,7 +163,12 @@ def main():
         r["load"] = q / sat if sat else None
         out["runs"].append(r)
         log(f"[serve] qps {q:.2f}: p50 {r['p50_s']:.3f}s p99 {r['p99_s']:.3f}s, {r['solves_per_s']:.2f} solves/s")
+        for d, v in r["per_lattice"].items():
+            log(f"[serve]   {d}: {v['requests']} requests, p50 {v['p50_s']:.3f}s p99 {v['p99_s']:.3f}s")
     print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(json.dumps(out) + "\n")
 
 
 if __name__ == "__main__":

@@ -56,3 +56,20 @@ def test_argument_validation_without_device(lib):
     # freeing NULL handles is a no-op
     for f in (b.bq_context_destroy, b.bq_gauge_free, b.bq_op_free, b.bq_field_free):
         assert f(None) == b.BQ_OK
+
+
+def test_solve_parameters_validated_before_any_handle_use(lib):
+    """bq_trace and bq_solve reject out-of-range precisions, solvers and tolerances before they touch
+    the operator, so a placeholder handle (never dereferenced) suffices on a host without a GPU."""
+    from paper_1711_03836_amd import bqhip as b
+    dummy = C.create_string_buffer(64)
+    h = C.cast(dummy, C.c_void_p)
+    t = (C.c_double * 2)()
+    for bad in ({"inner_prec": 3}, {"inner_prec": -1}, {"solver": 7}, {"tol": 0.0}, {"tol": float("nan")}):
+        kw = {"tol": 1e-10, "maxiter": 100, "inner_prec": b.BQ_F32, "delta": 0.0, "system": b.BQ_SYS_M, "chunk": 4,
+              "use_graph": 0, "solver": b.BQ_SOLVER_CG}
+        kw.update(bad)
+        prm = b.bq_solve_params(kw["tol"], kw["maxiter"], kw["inner_prec"], kw["delta"], kw["system"], kw["chunk"],
+                                kw["use_graph"], kw["solver"])
+        assert b.bq_trace(h, 1, 1, 1, C.byref(prm), t, t, None) == b.BQ_ERR_INVALID, bad
+        assert b.bq_solve(h, h, h, C.byref(prm), None, None) == b.BQ_ERR_INVALID, bad
