@@ -196,10 +196,13 @@ def main():
 
     k = dslash[args.inner]
     traffic, traffic_note = measured_traffic(dims, args.inner, nrhs, k["tune"])
+    copy_gbs = device_copy_gbs(stream)
     roof = {"bound": "hbm", "achieved": k["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": k["k1_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": f"K1 = T_ee^-1 D_eo, {args.inner}, {nrhs} columns, recon/R/bs={k['tune']}",
-            "bytes_per_launch": k["k1_bytes"], "traffic_source": traffic_note}
+            "kernel": f"K1 = T_ee^-1 D_eo, {args.inner}, {nrhs} columns, recon/R/bs/march/lds={k['tune']}",
+            "bytes_per_launch": k["k1_bytes"], "traffic_source": traffic_note,
+            "copy_gbs": copy_gbs, "frac_of_copy": k["k1_gbs"] / copy_gbs}
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s; K1 at {roof['frac_of_copy']:.1%} of it")
 
     serving = None
     if args.serve_requests > 0:
@@ -231,6 +234,25 @@ def main():
                   "bytes_per_solve": last_st["bytes"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def device_copy_gbs(stream, mib=2048, reps=10):
+    """Read + write rate of a plain 2 GiB device-to-device copy (torch), HIP events on `stream`."""
+    import torch
+    n = mib * (1 << 20) // 4
+    with torch.cuda.stream(stream):
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        c.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            c.copy_(a)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, c
+    return 2 * n * 4 / ms / 1e6
 
 
 def prefer_profiled_tune(bq, ctx, op, dims, inner, prec, nrhs):

@@ -26,7 +26,7 @@ def main():
     ap.add_argument("--dims", default="32,32,32,64")
     ap.add_argument("--prec", choices=list(PREC), default="f32")
     ap.add_argument("--nrhs", type=int, default=12)
-    ap.add_argument("--kind", default="K1")
+    ap.add_argument("--kind", default="K1", help="an operator kind (K1, MHAT, ...) or SOLVE")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--tune", default="auto", help="'auto' or recon,R,bs[,march[,lds]]")
     ap.add_argument("--eps", type=float, default=0.2)
@@ -77,7 +77,6 @@ def main():
 
     dims = tuple(int(v) for v in args.dims.split(","))
     prec = PREC[args.prec]
-    kind = getattr(bq, "BQ_OP_" + args.kind)
     U = inputs.gauge_field(dims, args.eps, seed=20171110)
     ctx = bq.Context(0)
     G = bq.Gauge(ctx, dims, U, t_bc=-1)
@@ -86,6 +85,22 @@ def main():
         op.autotune(prec, args.nrhs)
     else:
         ctx.tune_set(prec, args.nrhs, *(int(v) for v in args.tune.split(",")))
+    if args.kind == "SOLVE":
+        # one solve of M x = b for the 12 point sources (inner precision --prec, FP64 reliable updates),
+        # so that per-dispatch counters cover the CG iteration's kernels (K2 with the residual update,
+        # the vector updates, the reductions)
+        b = inputs.point_sources(dims)
+        fb = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, b.shape[0])
+        fx = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, b.shape[0])
+        fb.put(b)
+        rc, info = op.solve(fb, fx, 1e-10, system=bq.BQ_SYS_M, inner_prec=prec)
+        st = op.stats()
+        print(json.dumps({"kind": "SOLVE", "dims": dims, "prec": args.prec, "nrhs": b.shape[0],
+                          "tune": ctx.tune_get(prec, b.shape[0]), "ms": st["seconds"] * 1e3,
+                          "iters": max(i["iters"] for i in info), "launches": st["launches"],
+                          "true_rel_resid": max(i["true_rel_resid"] for i in info)}), flush=True)
+        return
+    kind = getattr(bq, "BQ_OP_" + args.kind)
     si, so = bq.OP_SUBSETS[kind]
     fi = bq.Field(ctx, dims, si, prec, args.nrhs)
     fo = bq.Field(ctx, dims, so, prec, args.nrhs)
