@@ -346,6 +346,12 @@ int bq_solve_stats_get(bq_op op, bq_solve_stats* out);
  * bytes one launch must move (each input read once, each output written once). */
 int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void* stream, double* ms, double* bytes);
 
+/* Reference rate of the device's memory (measurement aid, no counterpart in the paper): time
+ * `reps` launches of a plain copy of `bytes` (a multiple of 16) between two buffers the context
+ * allocates for the call, with HIP events on `stream` (NULL: the context's stream); *ms = mean
+ * per copy, which moves 2 * bytes.  Errors: BQ_ERR_INVALID, BQ_ERR_OOM, BQ_ERR_DEVICE. */
+int bq_time_copy(bq_context ctx, uint64_t bytes, int reps, void* stream, double* ms);
+
 /* Stencil configuration (the project's autotuner; no counterpart in the paper) used for a given
  * precision and column count (set by
  * bq_autotune or explicitly; otherwise a default).  recon: 12 or 18 reals per
@@ -362,9 +368,13 @@ int bq_time_apply(bq_op op, int kind, bq_field in, bq_field out, int reps, void*
  * from there by every wave (march is then ignored; bs may be any multiple of 64 up to 1024);
  * lds: 2 is the same with R = 1 only, where each wave also takes the x and y neighbours that
  * lie in its own tile from the other lanes' registers instead of from memory.
- * Results do not depend on the configuration. */
-int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march, int* lds);
-int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march, int lds);
+ * order: the traversal of the 64-site tiles by the plain and tile-shared stencils on lattices
+ * whose (x,y) planes hold whole tiles: 0 visits them in blocks of 4x4 (z,t) planes; 1 gives each
+ * of the 8 XCDs one slab of L_z/gcd(L_z,8) z planes and walks it t plane by t plane (ignored by
+ * the t-marching stencil and on other lattices).  Errors: BQ_ERR_INVALID for a configuration
+ * that is not compiled or out of range.  Results do not depend on the configuration. */
+int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march, int* lds, int* order);
+int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march, int lds, int order);
 /* Time the candidate configurations for (op's lattice, prec, nrhs) on op and keep the fastest. */
 int bq_autotune(bq_op op, int prec, int nrhs);
 

@@ -117,8 +117,10 @@ _sig = {
                                       _P(bq_solve_info)]),
     "bq_solve_stats_get": (C.c_int, [_h, _P(bq_solve_stats)]),
     "bq_time_apply": (C.c_int, [_h, C.c_int, _h, _h, C.c_int, C.c_void_p, _P(C.c_double), _P(C.c_double)]),
-    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)]),
-    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    "bq_time_copy": (C.c_int, [_h, C.c_uint64, C.c_int, C.c_void_p, _P(C.c_double)]),
+    "bq_tune_get": (C.c_int, [_h, C.c_int, C.c_int, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int),
+                              _P(C.c_int)]),
+    "bq_tune_set": (C.c_int, [_h, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
     "bq_server_create": (C.c_int, [_h, C.c_int, C.c_int, _P(_h)]),
     "bq_server_set_backfill": (C.c_int, [_h, C.c_int]),
@@ -210,14 +212,21 @@ class Context:
         check(bq_context_hbm_used(self.h, C.byref(v)))
         return v.value
 
-    def tune_get(self, prec, nrhs):
-        """(recon, R, bs, march, lds) of the stencil for this precision and column count."""
-        r, R, bs, m, l = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
-        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs), C.byref(m), C.byref(l)))
-        return r.value, R.value, bs.value, m.value, l.value
+    def time_copy(self, nbytes, reps=10, stream=None):
+        """Mean time (ms) of a plain device copy of nbytes (moving 2 * nbytes), HIP events on stream."""
+        ms = C.c_double()
+        check(bq_time_copy(self.h, int(nbytes), int(reps), _stream(stream), C.byref(ms)))
+        return ms.value
 
-    def tune_set(self, prec, nrhs, recon, R, bs, march=0, lds=0):
-        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs, march, lds))
+    def tune_get(self, prec, nrhs):
+        """(recon, R, bs, march, lds, order) of the stencil for this precision and column count."""
+        r, R, bs, m, l, o = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        check(bq_tune_get(self.h, prec, nrhs, C.byref(r), C.byref(R), C.byref(bs), C.byref(m), C.byref(l),
+                          C.byref(o)))
+        return r.value, R.value, bs.value, m.value, l.value, o.value
+
+    def tune_set(self, prec, nrhs, recon, R, bs, march=0, lds=0, order=0):
+        check(bq_tune_set(self.h, prec, nrhs, recon, R, bs, march, lds, order))
 
     def save_tuning(self, path, keys, lattice=None):
         """Write the stencil configurations of the (prec, nrhs) pairs in `keys` to a JSON file,

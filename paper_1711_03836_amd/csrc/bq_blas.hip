@@ -500,6 +500,22 @@ hipError_t launch_norm2(int prec, FieldArg x, int n, int ncol, double* partial, 
     return hipGetLastError();
 }
 
+// Plain copy of n 16-byte words, one word per thread, non-temporal on both sides: the reference
+// rate against which the stencils' HBM bandwidth is read.
+__global__ __launch_bounds__(256) void k_copy16(const bq_u4v* __restrict__ src, bq_u4v* __restrict__ dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_copy16(const void* src, void* dst, size_t n, hipStream_t st)
+{
+    const size_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, (const bq_u4v*)src, (bq_u4v*)dst, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(int prec, FieldArg x, int n, int ncol, const int* status, int statmask, hipStream_t st)
 {
     const dim3 grid = grid2(n, ncol);

@@ -100,6 +100,7 @@ hipError_t launch_convert(int src_prec, FieldArg src, int dst_prec, FieldArg dst
                           const int* status, int statmask, hipStream_t st);
 hipError_t launch_norm2(int prec, FieldArg x, int Vh, int ncol, double* partial, int nwaves, hipStream_t st);
 hipError_t launch_zero(int prec, FieldArg x, int Vh, int ncol, const int* status, int statmask, hipStream_t st);
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t st);  // n16 16-byte words
 // x += alpha p ; p = r + beta p   (CG; per column, by status)
 hipError_t launch_cg_update(int xprec, FieldArg x, int pprec, FieldArg p, int rprec, FieldArg r, int Vh, int ncol,
                             const double* alpha, const double* beta, const int* status, hipStream_t st);

@@ -90,11 +90,12 @@ def test_point_source_solve_oracle_residual(world):
 
 @pytest.mark.timeout(900)
 def test_trace_configuration_48x96_sampled():
-    """48^3x96 with 16 columns in the launch configuration the trace workload was tuned to (FP32,
-    two-row links, 2 columns per thread, 256 sites per workgroup, t-marching in segments of 4): FP32
-    Mhat at sampled odd sites, most on time and space boundaries.  The links are a 48^3x32 field
-    U = exp(0.15 i H) repeated three times along t; the 16 columns cycle through three Gaussian
-    fields, so a column read from a neighbouring column's storage would show."""
+    """48^3x96 with 16 columns in the launch configurations the trace workload takes (FP32, two-row
+    links: 2 columns per thread, 256 sites per workgroup, t-marching in segments of 4; and the
+    tile-shared stencil with 16 column waves per tile in the z-slab traversal): FP32 Mhat at sampled
+    odd sites, most on time and space boundaries.  The links are a 48^3x32 field U = exp(0.15 i H)
+    repeated three times along t; the 16 columns cycle through three Gaussian fields, so a column
+    read from a neighbouring column's storage would show."""
     import torch
     from paper_1711_03836_amd import bqhip as bq
     dims = (48, 48, 48, 96)
@@ -104,16 +105,22 @@ def test_trace_configuration_48x96_sampled():
     ctx = bq.Context(0)
     G = bq.Gauge(ctx, dims, U, -1)
     op = bq.Op(G, 0.1235, 1.9, 0.0)
-    ctx.tune_set(bq.BQ_F32, 16, 12, 2, 256, 4)
     psi3 = inputs.gaussian_spinor(dims, 3, seed=96)
     cols = [c % 3 for c in range(16)]
     dev = torch.from_numpy(psi3).to("cuda")[cols].contiguous()
     fi = bq.Field(ctx, dims, bq.BQ_ODD, bq.BQ_F32, 16)
     fo = bq.Field(ctx, dims, bq.BQ_ODD, bq.BQ_F32, 16)
     fi.put(dev)
-    op.apply(bq.BQ_OP_MHAT, fi, fo)
-    out = torch.zeros_like(dev)
-    fo.get(out)
+    outs = []
+    for tune in ((12, 2, 256, 4, 0, 0), (12, 1, 1024, 0, 1, 1)):
+        ctx.tune_set(bq.BQ_F32, 16, *tune)
+        op.apply(bq.BQ_OP_MHAT, fi, fo)
+        out = torch.zeros_like(dev)
+        fo.get(out)
+        outs.append(out)
+    assert torch.equal(outs[0], outs[1])
+    out = outs[0]
+    del outs
     rng = np.random.default_rng(4896)
     L = dims
     pts = [(1, 0, 0, 0), (0, 0, 0, 95), (47, 47, 47, 94), (0, 47, 0, 31), (1, 0, 47, 32), (0, 1, 0, 64)]
@@ -127,7 +134,8 @@ def test_trace_configuration_48x96_sampled():
     for c in range(16):
         err = np.abs(got[c] - want[cols[c]]).max() / np.abs(want[cols[c]]).max()
         assert err < 1e-5, (c, err)
-    print(f"[fullsize] 48^3x96 Mhat x16 (march 4) at {len(sites)} odd sites: ok", flush=True)
+    print(f"[fullsize] 48^3x96 Mhat x16 (march 4 and tile-shared, bitwise equal) at {len(sites)} odd sites: ok",
+          flush=True)
 
 
 @pytest.mark.timeout(600)

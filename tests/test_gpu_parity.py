@@ -359,7 +359,7 @@ def test_march_matches_plain_and_oracle(bq, dims, march, prec, recon, R, bs):
         out = {}
         for m in (0, march):
             ctx.tune_set(prec, nrhs, recon, R, bs, m)
-            assert ctx.tune_get(prec, nrhs) == (recon, R, bs, m, 0)
+            assert ctx.tune_get(prec, nrhs) == (recon, R, bs, m, 0, 0)
             fi = bq.Field(ctx, dims, si, prec, nrhs)
             fo = bq.Field(ctx, dims, so, prec, nrhs)
             fi.put(psi)
@@ -426,7 +426,7 @@ def test_tuning_json_roundtrip(bq, setup, tmp_path):
     ctx2 = bq.Context(0)
     assert ctx2.load_tuning(path) == [(bq.BQ_F32, 4), (bq.BQ_F64, 1)]
     assert ctx2.tune_get(bq.BQ_F32, 4) == ctx.tune_get(bq.BQ_F32, 4)
-    assert ctx2.tune_get(bq.BQ_F64, 1) == (18, 1, 256, 0, 0)
+    assert ctx2.tune_get(bq.BQ_F64, 1) == (18, 1, 256, 0, 0, 0)
     ctx2.close()
 
 
@@ -475,3 +475,49 @@ def test_tile_shared_matches_plain_and_oracle(bq, dims, prec, recon, R, nrhs, lb
         assert all(c["converged"] for c in info)
         xs[lds] = x
     assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("dims", [(8, 16, 8, 8), (8, 16, 6, 4)])
+@pytest.mark.parametrize("prec,recon,R,bs,lds", [(0, 18, 2, 128, 0), (1, 12, 3, 256, 0), (1, 12, 1, 768, 1),
+                                                  (2, 12, 1, 768, 1), (0, 12, 1, 768, 1)])
+def test_traversal_order_bitwise(bq, dims, prec, recon, R, bs, lds):
+    """Traversal order 1 (one z slab per XCD, walked t plane by t plane; on 8x16x6x4 slabs of 3 z
+    planes) visits the same tiles as order 0 and does each site's arithmetic in the same order:
+    every operator kind is bitwise the order-0 result and matches the oracle."""
+    nrhs = 12
+    U = inputs.gauge_field(dims, 0.3, seed=61)
+    ctx = bq.Context(0)
+    G = bq.Gauge(ctx, dims, U, -1)
+    op = bq.Op(G, 0.124, 1.5, 0.1)
+    ref = orc.Operator(dims, U, 0.124, 1.5, mu=0.1)
+    psi = inputs.gaussian_spinor(dims, nrhs, seed=62)
+    for name in MARCH_KINDS + ("MHAT", "DEO"):
+        kind = getattr(bq, "BQ_OP_" + name)
+        si, so = bq.OP_SUBSETS[kind]
+        out = {}
+        for order in (0, 1):
+            ctx.tune_set(prec, nrhs, recon, R, bs, 0, lds, order)
+            assert ctx.tune_get(prec, nrhs)[5] == order
+            fi = bq.Field(ctx, dims, si, prec, nrhs)
+            fo = bq.Field(ctx, dims, so, prec, nrhs)
+            fi.put(psi)
+            op.apply(kind, fi, fo)
+            out[order] = fo.get()
+        assert np.array_equal(out[0], out[1]), name
+        mask = {bq.BQ_EVEN: ref.parity == 0, bq.BQ_ODD: ref.parity == 1, bq.BQ_FULL: np.ones(ref.V, bool)}[so]
+        for c in (0, nrhs - 1):
+            want = oracle_apply(ref, kind, bq, psi[c])
+            assert maxrel(out[1][c][mask], want[mask]) < TOL[prec], (name, c)
+
+
+def test_time_copy(bq, setup):
+    """The plain device copy that serves as the bandwidth reference runs, moves data at a rate
+    between 1 and 8 TB/s (read + write) on one MI355X, and refuses sizes that are not whole 16-byte
+    words."""
+    ctx = setup[0]
+    nbytes = 256 << 20
+    ms = ctx.time_copy(nbytes, reps=5)
+    gbs = 2 * nbytes / ms / 1e6
+    assert 1000 < gbs < 8000, gbs
+    with pytest.raises(bq.BqError):
+        ctx.time_copy(15)

@@ -50,13 +50,13 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
 
 
 def test_tuning_file_round_trip(tmp_path):
-    """Context.save_tuning / load_tuning write and apply the (prec, nrhs) -> (recon, R, bs, march, lds)
+    """Context.save_tuning / load_tuning write and apply the (prec, nrhs) -> (recon, R, bs, march, lds, order)
     table through tune_get / tune_set only; checked here on stand-in contexts (no device)."""
     sys.path.insert(0, ROOT)
     from paper_1711_03836_amd import bqhip as bq
 
     class Src:
-        table = {(1, 12): (12, 1, 64, 0, 1), (0, 1): (18, 1, 64, 16, 0)}
+        table = {(1, 12): (12, 1, 64, 0, 1, 1), (0, 1): (18, 1, 64, 16, 0, 0)}
 
         def tune_get(self, prec, nrhs):
             return self.table[(prec, nrhs)]
@@ -65,8 +65,8 @@ def test_tuning_file_round_trip(tmp_path):
         def __init__(self):
             self.set = []
 
-        def tune_set(self, prec, nrhs, recon, R, bs, march=0, lds=0):
-            self.set.append((prec, nrhs, recon, R, bs, march, lds))
+        def tune_set(self, prec, nrhs, recon, R, bs, march=0, lds=0, order=0):
+            self.set.append((prec, nrhs, recon, R, bs, march, lds, order))
 
     path = tmp_path / "tune.json"
     bq.Context.save_tuning(Src(), path, [(1, 12), (0, 1)], lattice=(32, 32, 32, 64))
@@ -74,4 +74,4 @@ def test_tuning_file_round_trip(tmp_path):
     assert doc["lattice"] == [32, 32, 32, 64]
     dst = Dst()
     assert bq.Context.load_tuning(dst, path) == [(1, 12), (0, 1)]
-    assert dst.set == [(1, 12, 12, 1, 64, 0, 1), (0, 1, 18, 1, 64, 16, 0)]
+    assert dst.set == [(1, 12, 12, 1, 64, 0, 1, 1), (0, 1, 18, 1, 64, 16, 0, 0)]
