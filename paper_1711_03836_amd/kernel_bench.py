@@ -28,8 +28,12 @@ def main():
     ap.add_argument("--nrhs", type=int, default=12)
     ap.add_argument("--kind", default="K1", help="an operator kind (K1, MHAT, ...) or SOLVE")
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--tune", default="auto", help="'auto' or recon,R,bs[,march[,lds]]")
+    ap.add_argument("--tune", default="auto", help="'auto' or recon,R,bs[,march[,lds[,order]]]")
     ap.add_argument("--eps", type=float, default=0.2)
+    ap.add_argument("--kappa", type=float, default=0.124)
+    ap.add_argument("--csw", type=float, default=1.5)
+    ap.add_argument("--mu", type=float, default=0.1)
+    ap.add_argument("--tune64", default="auto", help="SOLVE: stencil configuration of the FP64 reliable updates")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--stream-mib", type=int, default=0, help="measure read / write / copy bandwidth of plain "
                     "torch kernels on N MiB and exit")
@@ -80,7 +84,7 @@ def main():
     U = inputs.gauge_field(dims, args.eps, seed=20171110)
     ctx = bq.Context(0)
     G = bq.Gauge(ctx, dims, U, t_bc=-1)
-    op = bq.Op(G, 0.124, 1.5, 0.1)
+    op = bq.Op(G, args.kappa, args.csw, args.mu)
     if args.tune == "auto":
         op.autotune(prec, args.nrhs)
     else:
@@ -90,13 +94,19 @@ def main():
         # so that per-dispatch counters cover the CG iteration's kernels (K2 with the residual update,
         # the vector updates, the reductions)
         b = inputs.point_sources(dims)
+        if prec != bq.BQ_F64:
+            if args.tune64 == "auto":
+                op.autotune(bq.BQ_F64, b.shape[0])
+            else:
+                ctx.tune_set(bq.BQ_F64, b.shape[0], *(int(v) for v in args.tune64.split(",")))
         fb = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, b.shape[0])
         fx = bq.Field(ctx, dims, bq.BQ_FULL, bq.BQ_F64, b.shape[0])
         fb.put(b)
         rc, info = op.solve(fb, fx, 1e-10, system=bq.BQ_SYS_M, inner_prec=prec)
         st = op.stats()
         print(json.dumps({"kind": "SOLVE", "dims": dims, "prec": args.prec, "nrhs": b.shape[0],
-                          "tune": ctx.tune_get(prec, b.shape[0]), "ms": st["seconds"] * 1e3,
+                          "tune": ctx.tune_get(prec, b.shape[0]), "tune64": ctx.tune_get(bq.BQ_F64, b.shape[0]),
+                          "ms": st["seconds"] * 1e3,
                           "iters": max(i["iters"] for i in info), "launches": st["launches"],
                           "true_rel_resid": max(i["true_rel_resid"] for i in info)}), flush=True)
         return

@@ -7,6 +7,9 @@
 `stats` turns the kernel statistics CSV of a `rocprofv3 --kernel-trace --stats --output-format csv`
 run into a table (calls, total, average per kernel).
 
+`kernels` reads the same two passes over a whole run (e.g. one solve) and tabulates the calibrated
+traffic per kernel name.
+
 `traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of kernel_bench (each with a
 plain device copy of --copy-mib MiB before the timed launches), takes the last --launches dispatches
 of the kernel whose name contains --kernel, and scales each counter by (known bytes of the copy) /
@@ -109,6 +112,41 @@ def traffic(args):
     print(json.dumps(out, indent=1))
 
 
+def kernels(args):
+    """Per-kernel HBM traffic over every dispatch of a run (e.g. one solve): FETCH_SIZE and WRITE_SIZE
+    summed per kernel name, each scaled by its copy calibration, as a text table."""
+    copy_bytes = args.copy_mib * (1 << 20)
+    per = {}
+    for counter, d in (("FETCH_SIZE", args.fetch_dir), ("WRITE_SIZE", args.write_dir)):
+        rows = _counter_rows(d, counter)
+        copies = [v for (_, name, _, v) in rows if "copyBuffer" in name and v > 0.25 * copy_bytes / 1024]
+        if not copies:
+            raise SystemExit(f"{counter}: no calibration copy found in {d}")
+        cal = (copy_bytes / 1024) / (sum(copies) / len(copies))
+        for _, name, _, v in rows:
+            if "copyBuffer" in name or "fillBuffer" in name:
+                continue
+            e = per.setdefault(name, {"FETCH_SIZE": [0, 0.0], "WRITE_SIZE": [0, 0.0]})
+            e[counter][0] += 1
+            e[counter][1] += v * 1024 * cal
+    total = sum(e["FETCH_SIZE"][1] + e["WRITE_SIZE"][1] for e in per.values())
+    lines = [f"# HBM traffic per kernel (copy-calibrated FETCH_SIZE + WRITE_SIZE): {args.title}", "",
+             "FETCH_SIZE pass:", "", "    " + args.command_fetch, "", "WRITE_SIZE pass:", "", "    " + args.command_write, "",
+             f"total {total / 1e9:.2f} GB over the run; stencil-kernel source digest {source_digest()}", "",
+             f"{'calls':>6} {'fetch GB':>9} {'write GB':>9} {'GB/call':>8} {'%':>6}  kernel"]
+    for name, e in sorted(per.items(), key=lambda kv: -(kv[1]["FETCH_SIZE"][1] + kv[1]["WRITE_SIZE"][1])):
+        n = max(e["FETCH_SIZE"][0], 1)
+        t = e["FETCH_SIZE"][1] + e["WRITE_SIZE"][1]
+        if t < args.min_fraction * total:
+            continue
+        short = name if len(name) <= args.width else name[:args.width] + "..."
+        lines.append(f"{n:6d} {e['FETCH_SIZE'][1] / 1e9:9.2f} {e['WRITE_SIZE'][1] / 1e9:9.2f} {t / n / 1e9:8.3f} "
+                     f"{100 * t / total:6.2f}  {short}")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -131,8 +169,18 @@ def main(argv=None):
     t.add_argument("--algorithmic-bytes", type=float, default=0.0)
     t.add_argument("--command-fetch", default="")
     t.add_argument("--command-write", default="")
+    k = sub.add_parser("kernels")
+    k.add_argument("fetch_dir")
+    k.add_argument("write_dir")
+    k.add_argument("out")
+    k.add_argument("--copy-mib", type=int, default=1024)
+    k.add_argument("--title", default="")
+    k.add_argument("--min-fraction", type=float, default=0.002)
+    k.add_argument("--width", type=int, default=110)
+    k.add_argument("--command-fetch", default="")
+    k.add_argument("--command-write", default="")
     args = ap.parse_args(argv)
-    {"stats": stats, "traffic": traffic}[args.cmd](args)
+    {"stats": stats, "traffic": traffic, "kernels": kernels}[args.cmd](args)
 
 
 if __name__ == "__main__":
