@@ -363,8 +363,8 @@ int bq_time_copy(bq_context ctx, uint64_t bytes, int reps, void* stream, double*
  * planes earlier (up to bs/64 column groups per workgroup).  It applies to
  * lattices whose (x,y) planes hold whole 64-site tiles and whose L_t it divides;
  * elsewhere the plain stencil runs.  lds: 1 selects the tile-shared stencil when a tile has
- * several column groups (nrhs > R): one 64-site tile per workgroup with up to bs/64 (at most 16)
- * column-group waves, whose links (rebuilt to 3x3) and clover are staged in LDS once and read
+ * several column groups (nrhs > R): one 64-site tile per workgroup with up to bs/64 (at most 16;
+ * FP64 at most 12) column-group waves, whose links (rebuilt to 3x3) and clover are staged in LDS once and read
  * from there by every wave (march is then ignored; bs may be any multiple of 64 up to 1024);
  * lds: 2 is the same with R = 1 only, where each wave also takes the x and y neighbours that
  * lie in its own tile from the other lanes' registers instead of from memory.

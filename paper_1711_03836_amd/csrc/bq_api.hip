@@ -103,7 +103,8 @@ static int fail(int code, const char* fmt, ...)
 struct Tune {
     int recon, R, bs;
     int march = 0;  // > 0: t-marching stencil with segments of this many time planes, where the lattice allows
-    int lds = 0;    // 1: tile-shared stencil (links and clover staged in LDS) for several column groups per tile
+    int lds = 0;    // 1: tile-shared stencil (links and clover staged in LDS) for several column groups per tile;
+                    // 2: with a lane exchange of x/y neighbours
     int order = 0;  // tile traversal of the plain and tile-shared stencils: 0 blocks of 4x4 (z,t) planes,
                     // 1 one z slab per XCD walked plane by plane in t
 };
@@ -2737,7 +2738,7 @@ int bq_autotune(bq_op op, int prec, int nrhs)
                     const int G = (nrhs + R - 1) / R;
                     if (waves > G && waves != 4) continue;  // bs / 64 is only a bound on the waves
                     if (mode == 2 && (R != 1 || waves < std::min(G, 16))) continue;
-                    if (prec == PREC_F64 && R > 1) continue;  // spills under the 1024-thread bound
+                    if (prec == PREC_F64 && R > 1) continue;  // spills under the 768-thread bound of FP64
                     const Tune t{recon, R, 64 * waves, 0, mode};
                     const double ms = time_of(t, 5);
                     if (ms < 1e300) cand.push_back({ms, t});

@@ -976,8 +976,11 @@ __device__ __forceinline__ void hh_step_lds(const Args<P, PR>& A, const Site& s,
     phase_end(act, acc);
 }
 
+// FP64 holds twice the registers per column: its workgroups stop at 12 column waves (768 threads)
+template <class P> constexpr int lds_max_threads() { return P::id == PREC_F64 ? 768 : 1024; }
+
 template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA, bool XCHG>
-__global__ __launch_bounds__(1024) void k_hop_lds(const Args<P, PR> A)
+__global__ __launch_bounds__(lds_max_threads<P>()) void k_hop_lds(const Args<P, PR> A)
 {
     using T = typename P::real;
     using LC = typename LinkLds<P>::C;
@@ -1160,7 +1163,7 @@ hipError_t launch_t(const HopLaunch& L, hipStream_t st)
         constexpr int lds_bytes = tile_lds_bytes<P, CL>();
         if (CL && L.clov == nullptr) return hipErrorInvalidValue;  // the epilogue needs a clover array
         A.tpb = 1;
-        A.gw = std::min(G, std::max(1, std::min(16, L.bs / kTile)));  // bs / 64 column-group waves at most
+        A.gw = std::min(G, std::max(1, std::min(lds_max_threads<P>() / kTile, L.bs / kTile)));  // bs / 64 waves at most
         A.nch = (G + A.gw - 1) / A.gw;
         A.gw = (G + A.nch - 1) / A.nch;  // balance the chunks
         A.nblk = L.g.ntiles;
