@@ -371,7 +371,9 @@ int bq_time_copy(bq_context ctx, uint64_t bytes, int reps, void* stream, double*
  * order: the traversal of the 64-site tiles by the plain and tile-shared stencils on lattices
  * whose (x,y) planes hold whole tiles: 0 visits them in blocks of 4x4 (z,t) planes; 1 gives each
  * of the 8 XCDs one slab of L_z/gcd(L_z,8) z planes and walks it t plane by t plane (ignored by
- * the t-marching stencil and on other lattices).  Errors: BQ_ERR_INVALID for a configuration
+ * the t-marching stencil and on other lattices); 2 is order 1 where it applies and, on any lattice
+ * with a multiple of 8 tile blocks, has each XCD walk its tile blocks once per column-group chunk
+ * (fewer columns in flight per XCD; links and clover are read once per chunk).  Errors: BQ_ERR_INVALID for a configuration
  * that is not compiled or out of range.  Results do not depend on the configuration. */
 int bq_tune_get(bq_context ctx, int prec, int nrhs, int* recon, int* R, int* bs, int* march, int* lds, int* order);
 int bq_tune_set(bq_context ctx, int prec, int nrhs, int recon, int R, int bs, int march, int lds, int order);

@@ -362,6 +362,9 @@ struct Geom {
     // flight are a few planes away instead of a whole time slice.  ntiles = tiles per parity.
     int ntiles, blocked, nu, zb, tb, nzb;
     float inv_nu, inv_zb, inv_tb, inv_nzb;
+    // Order of a launch's (tile block, column-group chunk) work items: 0 the chunks of a tile block
+    // one after another; 1 each XCD's share of tile blocks walked once per chunk (item_of)
+    int cmajor;
 };
 
 // exact quotient/remainder of n < 2^24 by d using a float reciprocal and one correction
@@ -436,6 +439,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
     int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Work item (tile block, column-group chunk) of logical block lb of a launch of nblk tile blocks x
+// nch chunks, lb from xcd_remap so that each XCD holds a contiguous range of nblk * nch / 8
+// blocks.  Chunk-major (g.cmajor, nblk a multiple of 8): an XCD walks its nblk / 8 tile blocks for
+// chunk 0, then for chunk 1, ..., so fewer columns are in flight on one XCD at a time; otherwise
+// the chunks of a tile block are adjacent and share its links and clover through the caches.
+__device__ __forceinline__ void item_of(const Geom& g, int lb, int nblk, int nch, int& tblk, int& chunk)
+{
+    if (g.cmajor && nch > 1 && (nblk & 7) == 0) {
+        const int per = nblk >> 3;
+        const int x = lb / (per * nch);
+        const int local = lb - x * per * nch;
+        chunk = local / per;
+        tblk = x * per + (local - chunk * per);
+    } else {
+        tblk = lb / nch;
+        chunk = lb - tblk * nch;
+    }
 }
 
 // CG column states (the solver's per-column state machine)

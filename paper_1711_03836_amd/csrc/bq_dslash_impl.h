@@ -818,8 +818,9 @@ template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA
 __global__ __launch_bounds__(512) void k_hop(const Args<P, PR> A)
 {
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int tblk = lb / A.nch;
-    hop_item<P, PR, R, DAG, EPI, RECON, PC, LA>(A, tblk, lb - tblk * A.nch);
+    int tblk, chunk;
+    item_of(A.g, lb, A.nblk, A.nch, tblk, chunk);
+    hop_item<P, PR, R, DAG, EPI, RECON, PC, LA>(A, tblk, chunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -990,8 +991,8 @@ __global__ __launch_bounds__(lds_max_threads<P>()) void k_hop_lds(const Args<P, 
     LC* lk = (LC*)smem;                               // [8 half hops][9][64]
     U* sc = (U*)(smem + 8 * 9 * kTile * sizeof(LC));  // [clover units][64]
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int lt = lb / A.nch;
-    const int chunk = lb - lt * A.nch;
+    int lt, chunk;
+    item_of(A.g, lb, A.nblk, A.nch, lt, chunk);
     const int tile = tile_at(A.g, lt);                // lt < ntiles: one tile per workgroup
     const int base = tile * kTile;
     // 1. stage the tile's links (8 half hops x 64 sites) and clover

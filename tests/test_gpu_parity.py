@@ -479,11 +479,12 @@ def test_tile_shared_matches_plain_and_oracle(bq, dims, prec, recon, R, nrhs, lb
 
 @pytest.mark.parametrize("dims", [(8, 16, 8, 8), (8, 16, 6, 4)])
 @pytest.mark.parametrize("prec,recon,R,bs,lds", [(0, 18, 2, 128, 0), (1, 12, 3, 256, 0), (1, 12, 1, 768, 1),
-                                                  (2, 12, 1, 768, 1), (0, 12, 1, 768, 1)])
+                                                  (1, 12, 1, 256, 1), (2, 12, 1, 384, 1), (0, 12, 1, 384, 1)])
 def test_traversal_order_bitwise(bq, dims, prec, recon, R, bs, lds):
     """Traversal order 1 (one z slab per XCD, walked t plane by t plane; on 8x16x6x4 slabs of 3 z
-    planes) visits the same tiles as order 0 and does each site's arithmetic in the same order:
-    every operator kind is bitwise the order-0 result and matches the oracle."""
+    planes) and order 2 (the same with each XCD walking its tiles once per column-group chunk) visit
+    the same work items as order 0 and do each site's arithmetic in the same order: every operator
+    kind is bitwise the order-0 result and matches the oracle."""
     nrhs = 12
     U = inputs.gauge_field(dims, 0.3, seed=61)
     ctx = bq.Context(0)
@@ -495,7 +496,7 @@ def test_traversal_order_bitwise(bq, dims, prec, recon, R, bs, lds):
         kind = getattr(bq, "BQ_OP_" + name)
         si, so = bq.OP_SUBSETS[kind]
         out = {}
-        for order in (0, 1):
+        for order in (0, 1, 2):
             ctx.tune_set(prec, nrhs, recon, R, bs, 0, lds, order)
             assert ctx.tune_get(prec, nrhs)[5] == order
             fi = bq.Field(ctx, dims, si, prec, nrhs)
@@ -503,11 +504,11 @@ def test_traversal_order_bitwise(bq, dims, prec, recon, R, bs, lds):
             fi.put(psi)
             op.apply(kind, fi, fo)
             out[order] = fo.get()
-        assert np.array_equal(out[0], out[1]), name
+        assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2]), name
         mask = {bq.BQ_EVEN: ref.parity == 0, bq.BQ_ODD: ref.parity == 1, bq.BQ_FULL: np.ones(ref.V, bool)}[so]
         for c in (0, nrhs - 1):
             want = oracle_apply(ref, kind, bq, psi[c])
-            assert maxrel(out[1][c][mask], want[mask]) < TOL[prec], (name, c)
+            assert maxrel(out[2][c][mask], want[mask]) < TOL[prec], (name, c)
 
 
 def test_time_copy(bq, setup):
