@@ -993,6 +993,14 @@ __global__ __launch_bounds__(lds_max_threads<P>()) void k_hop_lds(const Args<P, 
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     int lt, chunk;
     item_of(A.g, lb, A.nblk, A.nch, lt, chunk);
+    {
+        // A workgroup none of whose columns is selected (a reliable-update pass over a few columns)
+        // stages nothing; the test is the same for every thread of the workgroup.
+        bool sel = false;
+        for (int c = chunk * A.gw * R; c < (chunk + 1) * A.gw * R && c < A.ncol; c++)
+            sel |= col_selected(A.status, A.statmask, c);
+        if (!sel) return;
+    }
     const int tile = tile_at(A.g, lt);                // lt < ntiles: one tile per workgroup
     const int base = tile * kTile;
     // 1. stage the tile's links (8 half hops x 64 sites) and clover
