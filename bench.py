@@ -28,6 +28,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The serving leg runs one stream per server session: give them hardware queues of their own
+# (streams that share one run in submission order).  Set before the HIP runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 METRIC = "EO-clover Dslash GB/s (%HBM peak); mixed vs FP64 CG time-to-1e-10; p99 latency"
 HBM_PEAK_GBS = 8000.0
 PREC_NAMES = {"f64": 0, "f32": 1, "f16": 2}

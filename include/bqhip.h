@@ -385,19 +385,25 @@ int bq_autotune(bq_op op, int prec, int nrhs);
  * The paper has no serving layer; the server batches solves of the cg solver (section
  * "Algorithms") from many callers.
  * Requests M x = b (the BQ_SYS_M system) on resident gauge fields are queued by
- * bq_server_submit and advanced by bq_server_step: each step admits queued
- * requests into free column slots of the session of their gauge field (one
- * session per gauge field, mu and inner precision, `slots` columns each) when
- * their operator fits in the context's HBM budget, runs one chunk of CG
- * iterations on every session (sessions overlap on the device), and retires the
- * requests whose columns have converged.  Columns of one session have their own
+ * bq_server_submit and advanced by bq_server_step.  Requests run in sessions (one
+ * per gauge field, mu and inner precision, `slots` columns each) that advance
+ * independently, one chunk of CG iterations at a time, on streams of their own:
+ * a step retires the requests whose columns have converged in the sessions whose
+ * chunk has finished, admits queued requests into free column slots of those
+ * sessions when their operator fits in the context's HBM budget, and starts
+ * their next chunk.  Columns of one session have their own
  * kappa and clover and share the link reads; a request gives the same result
- * alone and batched with others.  Single host thread per server.
+ * alone and batched with others.  Single host thread per server.  Sessions overlap
+ * only on separate hardware queues: HIP maps a process's streams onto
+ * GPU_MAX_HW_QUEUES queues (4 unless set before the runtime starts), and streams
+ * that share a queue run in submission order, so a process serving k sessions
+ * should set it to k + 2 or more (its own stream and the context's).
  * ------------------------------------------------------------------------- */
 int bq_server_create(bq_context ctx, int slots, int chunk, bq_server* out);
 /* Admission order within a session: a request that does not fit (too few free slots, or its
  * operator over the HBM budget) waits at the head of its session's queue; later requests that
- * do fit may pass it for up to `steps` scheduling steps (backfill), after which the session
+ * do fit may pass it (backfill) in up to `steps` scheduling steps that admit into its session;
+ * steps in which the session has a chunk in flight do not count.  After that the session
  * admits nothing else until the waiting request fits.  0 = strict arrival order.  Default 8. */
 int bq_server_set_backfill(bq_server s, int steps);
 /* b: nrhs canonical spinors; x: an array of the same size that receives the solutions.
@@ -410,8 +416,10 @@ int bq_server_set_backfill(bq_server s, int steps);
  * finished by the step that tries to admit it, with that status. */
 int bq_server_submit(bq_server s, bq_gauge g, double kappa, double csw, double mu, const double* b, double* x,
                      int nrhs, double tol, int inner_prec, int maxiter, uint64_t* ticket);
-/* One scheduling step; up to max_done tickets completed in this step are written to
- * done_tickets, *ndone = their number. */
+/* One scheduling step.  It returns once at least one session's chunk has finished since
+ * the step began (waiting for one if none had), or at once when no chunk is in flight;
+ * chunks started by the step are still running when it returns.  Up to max_done tickets
+ * completed in this step are written to done_tickets, *ndone = their number. */
 int bq_server_step(bq_server s, uint64_t* done_tickets, int max_done, int* ndone);
 /* BQ_PENDING while queued or running; afterwards the request's status (info[nrhs]
  * filled) and the ticket is forgotten. */

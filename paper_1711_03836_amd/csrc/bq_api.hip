@@ -13,14 +13,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "bq_kernels.h"
@@ -1700,7 +1704,42 @@ int bq_gauge_free(bq_gauge g)
 // T = 1 + kappa c_SW B and the Cholesky inverse of its blocks.
 // lean_prec >= 0 builds only what a solve in that inner precision needs: FP64 T on both
 // parities and T_ee^-1, plus T_oo and T_ee^-1 in lean_prec.
-static int op_build(bq_gauge g, double kappa, double csw, double mu, int lean_prec, bq_op* out)
+// The clover arrays of an operator for kappa and c_SW from the gauge field's kappa-independent B
+// (Eq. 2), into arrays op_build allocated for the same lean precision, on stream st; then waits
+// for st.  flag: one device int for the positive-definiteness check.
+static int clover_fill(bq_op op, double kappa, double csw, int lean_prec, int* flag, hipStream_t st)
+{
+    bq_gauge g = op->gauge;
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    for (int p = 0; p < 2; p++) {
+        const bool inv = lean_prec < 0 || p == 0;
+        HIPCHK(launch_clover_from_B(g->g, p, g->B[p].as<double2>(), kappa * csw, op->T[PREC_F64][p].as<double2>(),
+                                    inv ? op->Tinv[PREC_F64][p].as<double2>() : nullptr, flag, st));
+    }
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hbad) return fail(BQ_ERR_CLOVER_NOT_HPD, "clover block not positive definite (kappa*c_SW = %g)", kappa * csw);
+    for (int prec : {PREC_F32, PREC_F16}) {
+        if (lean_prec >= 0 && prec != lean_prec) continue;
+        for (int p = 0; p < 2; p++) {
+            if (lean_prec < 0 || p == 1)
+                HIPCHK(launch_clover_convert(prec, op->T[PREC_F64][p].as<double2>(), op->T[prec][p].p, g->g.Vh, st));
+            if (lean_prec < 0 || p == 0)
+                HIPCHK(launch_clover_convert(prec, op->Tinv[PREC_F64][p].as<double2>(), op->Tinv[prec][p].p, g->g.Vh,
+                                             st));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    op->kappa = kappa;
+    op->csw = csw;
+    return BQ_OK;
+}
+
+// flag, st: a device int for the positive-definiteness check and the stream to build on (a server
+// session's); NULL: a flag of its own and the context stream.
+static int op_build(bq_gauge g, double kappa, double csw, double mu, int lean_prec, bq_op* out,
+                    int* flag = nullptr, hipStream_t st = nullptr)
 {
     if (!g || !out) return fail(BQ_ERR_INVALID, "NULL argument");
     *out = nullptr;
@@ -1717,44 +1756,36 @@ static int op_build(bq_gauge g, double kappa, double csw, double mu, int lean_pr
         for (int k = 0; k < 8; k++) cb.U64[k] = (const double2*)ls->U[k];
         for (int p = 0; p < 2; p++) cb.B[p] = g->B[p].as<double2>();
         HIPCHK(launch_clover_build(cb, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));  // B is read on the build stream below
     }
     auto op = std::make_unique<bq_op_s>();
     op->gauge = g;
-    op->kappa = kappa;
-    op->csw = csw;
     op->mu = mu;
-    DevBuf bad;
-    CHK(bad.alloc(ctx, sizeof(int)));
     for (int p = 0; p < 2; p++) {
         CHK(op->T[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
-        const bool inv = lean_prec < 0 || p == 0;
-        if (inv) CHK(op->Tinv[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
-        HIPCHK(launch_clover_from_B(g->g, p, g->B[p].as<double2>(), kappa * csw, op->T[PREC_F64][p].as<double2>(),
-                                    inv ? op->Tinv[PREC_F64][p].as<double2>() : nullptr, bad.as<int>(), ctx->stream));
+        if (lean_prec < 0 || p == 0) CHK(op->Tinv[PREC_F64][p].alloc(ctx, Vp * 36 * 16));
     }
-    int hbad = 0;
-    HIPCHK(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (hbad) return fail(BQ_ERR_CLOVER_NOT_HPD, "clover block not positive definite (kappa*c_SW = %g)", kappa * csw);
     for (int prec : {PREC_F32, PREC_F16}) {
         if (lean_prec >= 0 && prec != lean_prec) continue;
         const size_t bytes = Vp * clover_nu(prec) * unit_bytes(prec);
         for (int p = 0; p < 2; p++) {
-            if (lean_prec < 0 || p == 1) {
-                CHK(op->T[prec][p].alloc(ctx, bytes));
-                HIPCHK(launch_clover_convert(prec, op->T[PREC_F64][p].as<double2>(), op->T[prec][p].p, g->g.Vh,
-                                             ctx->stream));
-            }
-            if (lean_prec < 0 || p == 0) {
-                CHK(op->Tinv[prec][p].alloc(ctx, bytes));
-                HIPCHK(launch_clover_convert(prec, op->Tinv[PREC_F64][p].as<double2>(), op->Tinv[prec][p].p, g->g.Vh,
-                                             ctx->stream));
-            }
+            if (lean_prec < 0 || p == 1) CHK(op->T[prec][p].alloc(ctx, bytes));
+            if (lean_prec < 0 || p == 0) CHK(op->Tinv[prec][p].alloc(ctx, bytes));
         }
     }
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    g->nops++;
-    *out = op.release();
+    DevBuf own;
+    if (!flag) {
+        CHK(own.alloc(ctx, sizeof(int)));
+        flag = own.as<int>();
+    }
+    g->nops++;  // from here the operator is whole: freeing it releases this count
+    bq_op o = op.release();
+    const int rc = clover_fill(o, kappa, csw, lean_prec, flag, st ? st : ctx->stream);
+    if (rc != BQ_OK) {
+        bq_op_free(o);
+        return rc;
+    }
+    *out = o;
     return BQ_OK;
 }
 
@@ -2791,15 +2822,20 @@ int bq_autotune(bq_op op, int prec, int nrhs)
 // continuous-batching server
 //
 // One session per (gauge field, mu, inner precision): a multi-column CG workspace of `cap`
-// column slots on its own stream.  Each step
-//   1. admits queued requests whose columns fit in free slots and whose operator fits in
-//      the HBM budget: the operator (clover for the request's kappa) is built from the
-//      gauge field's kappa-independent B, the source is copied into the slots and prepared
-//      (bhat, b' = Mhat^dag bhat) on the device for the new columns only;
-//   2. runs one chunk of CG iterations plus a reliable-update pass on every session, all
-//      sessions launched before any is waited on, so that their work overlaps on the GPU;
-//   3. retires requests whose columns are done: reconstruction of the even sites, FP64
-//      residual check, copy-out, slots and operator freed.
+// column slots on its own stream.  Sessions advance independently, one chunk of CG
+// iterations plus a reliable-update pass at a time, each chunk ending in an event.  A step
+//   1. collects every session whose chunk has finished (event query, no wait) and retires
+//      the requests whose columns are done: reconstruction of the even sites, FP64 residual
+//      check, copy-out, slots and operator freed;
+//   2. admits queued requests into the idle sessions when their columns fit in free slots
+//      and their operator fits in the HBM budget: the operator (clover for the request's
+//      kappa) is built from the gauge field's kappa-independent B, the source is copied
+//      into the slots and prepared (bhat, b' = Mhat^dag bhat) on the device for the new
+//      columns only;
+//   3. launches the next chunk on every idle session with work.
+// If no chunk had finished, the step waits until one does and repeats 1-3 once, so a step
+// is one unit of progress.  A small lattice's session runs many chunks while a large
+// lattice's session runs one, instead of every session moving in lockstep with the slowest.
 // Columns of one batch have their own kappa and clover (per-column stencil launches) and
 // share the links.  A column's arithmetic does not depend on the other columns, and it
 // enters at a chunk boundary, so its result is the same alone and in the mix.
@@ -2841,9 +2877,18 @@ struct Session {
     int* hflags = nullptr;     // pinned: selection flags (cap ints) then per-column tol^2 (cap doubles)
     double* htol2 = nullptr;
     int used = 0;
+    hipEvent_t ev = nullptr;  // recorded after each chunk and its status copy-back
+    bool busy = false;        // a chunk is in flight
+    // Operators of retired requests, kept with their clover arrays: a new request refills one for
+    // its kappa and c_SW.  Freeing device memory waits for the whole device, which would stall
+    // every other session at each retirement.
+    std::vector<bq_op> spare;
+    DevBuf flag;  // positive-definiteness flag of the clover builds on this session's stream
     ~Session()
     {
         if (st) (void)hipStreamSynchronize(st);
+        for (bq_op o : spare) (void)bq_op_free(o);
+        if (ev) (void)hipEventDestroy(ev);
         if (hflags) (void)hipHostFree(hflags);
         if (st) (void)hipStreamDestroy(st);
         if (g) g->nsess--;
@@ -2889,9 +2934,11 @@ static int session_get(bq_server S, bq_gauge g, double mu, int prec, Session** o
     CHK(alloc_vec(ctx, g->g, PREC_F64, 2, s->cap, s->dbf, s->sbf, s->bfull));
     CHK(alloc_vec(ctx, g->g, PREC_F64, 2, s->cap, s->dxf, s->sxf, s->xfull));
     CHK(s->dflags.alloc(ctx, sizeof(int) * s->cap + sizeof(double) * s->cap));
+    CHK(s->flag.alloc(ctx, sizeof(int)));
     HIPCHK(hipHostMalloc((void**)&s->hflags, sizeof(int) * s->cap + sizeof(double) * s->cap));
     s->htol2 = (double*)(s->hflags + s->cap);
     HIPCHK(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
     s->slot.assign(s->cap, nullptr);
     // every slot starts empty: status DONE is inactive for every kernel
     std::vector<int> st(s->cap, COL_DONE);
@@ -2909,7 +2956,19 @@ static int admit(bq_server S, Request* q, Session* s)
 {
     bq_context ctx = S->ctx;
     const Geom& g = s->g->g;
-    CHK(op_build(q->g, q->kappa, q->csw, q->mu, s->prec == PREC_F64 ? PREC_F64 : s->prec, &q->op));
+    if (!s->spare.empty()) {
+        bq_op o = s->spare.back();
+        s->spare.pop_back();
+        const int rc = clover_fill(o, q->kappa, q->csw, s->prec, s->flag.as<int>(), s->st);
+        if (rc != BQ_OK) {
+            s->spare.push_back(o);
+            return rc;
+        }
+        o->mu = q->mu;
+        q->op = o;
+    } else {
+        CHK(op_build(q->g, q->kappa, q->csw, q->mu, s->prec, &q->op, s->flag.as<int>(), s->st));
+    }
     const size_t V = 2 * (size_t)g.Vh;
     const size_t bytes = (size_t)q->nrhs * V * 12 * 16;
     if (s->stage.bytes < bytes) CHK(s->stage.alloc(ctx, bytes));
@@ -3041,7 +3100,7 @@ static int retire(bq_server S, Session* s, std::vector<Request*>& done)
             for (int pr = 0; pr < 3; pr++) s->ct.T[pr][0][c] = s->ct.T[pr][1][c] = s->ct.Tinv[pr][0][c] = nullptr;
         }
         s->used -= q->nrhs;
-        bq_op_free(q->op);
+        s->spare.push_back(q->op);
         q->op = nullptr;
         q->state = REQ_DONE;
     }
@@ -3115,32 +3174,86 @@ static void unadmit(Request* q, Session* s)
         s->hflags[c] = 0;
         for (int pr = 0; pr < 3; pr++) s->ct.T[pr][0][c] = s->ct.T[pr][1][c] = s->ct.Tinv[pr][0][c] = nullptr;
     }
-    if (q->op) bq_op_free(q->op);
+    if (q->op) s->spare.push_back(q->op);
     q->op = nullptr;
     q->slots.clear();
     q->sess = nullptr;
     q->state = REQ_QUEUED;
 }
 
-int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone)
+// Free the spare operators of every session, when the HBM budget needs their memory; true if
+// there were any.  No work in flight reads a spare operator.
+static bool trim_spares(bq_server S)
 {
-    if (!S || !ndone) return fail(BQ_ERR_INVALID, "NULL argument");
-    *ndone = 0;
-    bq_context ctx = S->ctx;
-    HIPCHK(hipSetDevice(ctx->device));
-    auto report = [&](Request* q) {
-        if (*ndone < max_done && done_tickets) done_tickets[*ndone] = q->ticket;
-        (*ndone)++;
-    };
-    // 1. admission in arrival order per session.  A request that does not fit waits at the head
-    //    of its session; later, narrower requests may pass it (backfill) until it has waited
-    //    S->backfill steps, after which the session admits nothing else until it fits.
+    bool any = false;
+    for (auto& sp : S->sessions) {
+        for (bq_op o : sp->spare) (void)bq_op_free(o);
+        any |= !sp->spare.empty();
+        sp->spare.clear();
+    }
+    return any;
+}
+
+// the requests of session s whose columns are all done, stopped or out of iterations, from the
+// status copied back at the end of its last chunk; they retire and are reported
+static int collect(bq_server S, Session* s, const std::function<void(Request*)>& report)
+{
+    const int* hs = s->w.h_status;
+    std::vector<Request*> done;
+    for (int c = 0; c < s->cap; c++) {
+        Request* q = s->slot[c];
+        if (!q || std::find(done.begin(), done.end(), q) != done.end()) continue;
+        bool fin = true;
+        for (int cc : q->slots) {
+            const int stc = hs[cc];
+            const bool out_of_iters = hs[s->cap + cc] >= q->maxiter;
+            if (!(stc == COL_DONE || stc == COL_FAILED || out_of_iters)) fin = false;
+        }
+        if (fin) done.push_back(q);
+    }
+    if (!done.empty()) {
+        CHK(retire(S, s, done));
+        for (Request* q : done) report(q);
+    }
+    return BQ_OK;
+}
+
+// 1. of the step: sessions whose chunk has finished become idle and retire what it completed.
+// With `wait`, first wait (polling the events) until at least one busy session has finished.
+static int poll_sessions(bq_server S, bool wait, bool* progressed, const std::function<void(Request*)>& report)
+{
+    for (;;) {
+        for (auto& sp : S->sessions) {
+            Session* s = sp.get();
+            if (!s->busy) continue;
+            const hipError_t e = hipEventQuery(s->ev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return fail(BQ_ERR_DEVICE, "server chunk: %s", hipGetErrorString(e));
+            s->busy = false;
+            *progressed = true;
+            CHK(collect(S, s, report));
+        }
+        if (!wait || *progressed) return BQ_OK;
+        bool any = false;
+        for (auto& sp : S->sessions) any |= sp->busy;
+        if (!any) return BQ_OK;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+// 2. of the step: admission in arrival order per idle session.  A request that does not fit waits
+// at the head of its session; later, narrower requests may pass it (backfill) until it has waited
+// S->backfill steps, after which the session admits nothing else until it fits.  Requests of a
+// session with a chunk in flight stay queued without waiting a step.
+static int admit_queued(bq_server S, std::set<Request*>& blocked, const std::function<void(Request*)>& report)
+{
     std::vector<Session*> fresh;
     std::vector<Request*> keep;
-    std::map<Session*, Request*> head;  // first blocked request per session this step
+    std::map<Session*, Request*> head;  // first blocked request per session
     for (Request* q : S->queue) {
         Session* s = nullptr;
         int rc = session_get(S, q->g, q->mu, q->prec, &s);
+        if (rc == BQ_ERR_OOM && trim_spares(S)) rc = session_get(S, q->g, q->mu, q->prec, &s);
         if (rc == BQ_ERR_OOM) {
             keep.push_back(q);
             continue;
@@ -3148,6 +3261,10 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
         if (rc != BQ_OK) {
             finish_failed(q, rc);
             report(q);
+            continue;
+        }
+        if (s->busy) {
+            keep.push_back(q);
             continue;
         }
         Request*& h = head[s];
@@ -3163,6 +3280,10 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
             fresh.push_back(s);
         }
         rc = admit(S, q, s);
+        if (rc == BQ_ERR_OOM) {  // no room for the operator: free the spare ones and try again
+            unadmit(q, s);
+            if (trim_spares(S)) rc = admit(S, q, s);
+        }
         if (rc == BQ_ERR_OOM) {  // no room for the operator now: undo and wait
             unadmit(q, s);
             if (h == nullptr) h = q;
@@ -3177,44 +3298,54 @@ int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone
         }
     }
     for (auto& kv : head)
-        if (kv.second) kv.second->waited++;
+        if (kv.second) blocked.insert(kv.second);
     S->queue = keep;
     for (Session* s : fresh) {
         bool any = false;
         for (int c = 0; c < s->cap; c++) any |= s->hflags[c] != 0;
         if (any) CHK(prepare_new(s));
     }
-    // 2. one chunk on every session with work, all launched before any wait
-    std::vector<Session*> run;
-    for (auto& s : S->sessions)
-        if (s->used > 0) {
-            Workspace* w = &s->w;
-            w->cs.delta2 = s->prec == PREC_F64 ? 0.0 : 0.01;  // reliable-update threshold delta = 0.1
-            CHK(chunk(&s->stub, w, s->prec, S->chunk, s->st));
-            HIPCHK(hipMemcpyAsync(w->h_status, w->cs.status, sizeof(int) * 4 * s->cap, hipMemcpyDeviceToHost, s->st));
-            run.push_back(s.get());
-        }
-    // 3. retire finished requests
-    for (Session* s : run) {
-        HIPCHK(hipStreamSynchronize(s->st));
-        const int* hs = s->w.h_status;
-        std::vector<Request*> done;
-        for (int c = 0; c < s->cap; c++) {
-            Request* q = s->slot[c];
-            if (!q || std::find(done.begin(), done.end(), q) != done.end()) continue;
-            bool fin = true;
-            for (int cc : q->slots) {
-                const int stc = hs[cc];
-                const bool out_of_iters = hs[s->cap + cc] >= q->maxiter;
-                if (!(stc == COL_DONE || stc == COL_FAILED || out_of_iters)) fin = false;
-            }
-            if (fin) done.push_back(q);
-        }
-        if (!done.empty()) {
-            CHK(retire(S, s, done));
-            for (Request* q : done) report(q);
-        }
+    return BQ_OK;
+}
+
+// 3. of the step: the next chunk on every idle session with work, ending in its event
+static int launch_idle(bq_server S)
+{
+    for (auto& sp : S->sessions) {
+        Session* s = sp.get();
+        if (s->busy || s->used == 0) continue;
+        Workspace* w = &s->w;
+        w->cs.delta2 = s->prec == PREC_F64 ? 0.0 : 0.01;  // reliable-update threshold delta = 0.1
+        CHK(chunk(&s->stub, w, s->prec, S->chunk, s->st));
+        HIPCHK(hipMemcpyAsync(w->h_status, w->cs.status, sizeof(int) * 4 * s->cap, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipEventRecord(s->ev, s->st));
+        s->busy = true;
     }
+    return BQ_OK;
+}
+
+int bq_server_step(bq_server S, uint64_t* done_tickets, int max_done, int* ndone)
+{
+    if (!S || !ndone) return fail(BQ_ERR_INVALID, "NULL argument");
+    *ndone = 0;
+    bq_context ctx = S->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    const std::function<void(Request*)> report = [&](Request* q) {
+        if (*ndone < max_done && done_tickets) done_tickets[*ndone] = q->ticket;
+        (*ndone)++;
+    };
+    std::set<Request*> blocked;  // heads that could not be admitted: each waits one step
+    bool progressed = false;
+    for (int pass = 0; pass < 2; pass++) {
+        CHK(poll_sessions(S, pass == 1, &progressed, report));
+        CHK(admit_queued(S, blocked, report));
+        CHK(launch_idle(S));
+        bool any = false;
+        for (auto& sp : S->sessions) any |= sp->busy;
+        if (progressed || !any) break;
+    }
+    for (Request* q : blocked)
+        if (q->state == REQ_QUEUED) q->waited++;
     return BQ_OK;
 }
 

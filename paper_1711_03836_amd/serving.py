@@ -25,6 +25,13 @@ import time
 
 import numpy as np
 
+# Every server session runs on a stream of its own.  HIP maps a process's streams onto a fixed
+# number of hardware queues (4 unless set), and streams that share a queue run in submission
+# order: a small lattice's chunk would then wait behind a large lattice's kernels.  Four
+# sessions, the context stream and torch's stream need 8.  Effective only when set before the
+# HIP runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

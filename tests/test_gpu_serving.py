@@ -146,29 +146,38 @@ def _run_to_done(srv, tickets, limit=2000):
 
 def test_server_admission_by_hbm_budget():
     """With a context budget that holds the session and one request's operator but not two, the second
-    request waits until the first retires, then completes bitwise equal to its result alone."""
+    request waits until the first retires, then completes (in the first one's recycled operator) bitwise
+    equal to its result alone."""
     from paper_1711_03836_amd import bqhip as bq
     U = inputs.gauge_field(DIMS_A, 0.2, seed=61)
     ba = inputs.gaussian_spinor(DIMS_A, 1, seed=540)
     bb = inputs.gaussian_spinor(DIMS_A, 1, seed=541)
-    # measure: everything held while one request runs, and after it retires (the operator freed)
+    # measure: everything held while one request runs, then while two run side by side
     big = bq.Context(0)
     g = bq.Gauge(big, DIMS_A, U)
     srv = bq.Server(big, 4, 4)
     ta = srv.submit(g, ba, 0.12, 1.5)
     srv.step()
     assert srv.pending() == (0, 1)
-    used_running = big.hbm_used()
-    alone_a = _run_to_done(srv, [ta])
-    used_idle = big.hbm_used()
+    used_one = big.hbm_used()
+    alone_a = _run_to_done(srv, [ta])[ta]
+    srv.close()
+    srv = bq.Server(big, 4, 4)
     tb = srv.submit(g, bb, 0.121, 1.5)
-    alone_b = _run_to_done(srv, [tb])
-    op_bytes = used_running - used_idle
+    alone_b = _run_to_done(srv, [tb])[tb]
+    srv.close()
+    srv = bq.Server(big, 4, 4)
+    ta = srv.submit(g, ba, 0.12, 1.5)
+    tb = srv.submit(g, bb, 0.121, 1.5)
+    srv.step()
+    assert srv.pending() == (0, 2)
+    op_bytes = big.hbm_used() - used_one
     assert op_bytes > 0
+    _run_to_done(srv, [ta, tb])
     srv.close()
     srv = None
     # the same work under a budget with room for 1.5 operators
-    ctx = bq.Context(0, hbm_budget=used_idle + op_bytes * 3 // 2)
+    ctx = bq.Context(0, hbm_budget=used_one + op_bytes // 2)
     g2 = bq.Gauge(ctx, DIMS_A, U)
     srv = bq.Server(ctx, 4, 4)
     ta = srv.submit(g2, ba, 0.12, 1.5)
@@ -177,8 +186,43 @@ def test_server_admission_by_hbm_budget():
     assert srv.pending() == (1, 1)  # b waits for memory, not for slots (4 slots, 2 columns)
     res = _run_to_done(srv, [ta, tb])
     assert res[ta][0] == res[tb][0] == bq.BQ_OK
-    assert np.array_equal(res[ta][2], alone_a[ta][2])
-    assert np.array_equal(res[tb][2], alone_b[tb][2])
+    assert np.array_equal(res[ta][2], alone_a[2])
+    assert np.array_equal(res[tb][2], alone_b[2])
+    srv.close()
+
+
+def test_server_spare_operators_freed_for_budget():
+    """A retired request's operator is kept for the next request of its session; when another session
+    needs that memory under the budget, the kept operator is freed and the request is admitted."""
+    from paper_1711_03836_amd import bqhip as bq
+    U = inputs.gauge_field(DIMS_A, 0.2, seed=61)
+    b32 = inputs.gaussian_spinor(DIMS_A, 1, seed=545)
+    b64 = inputs.gaussian_spinor(DIMS_A, 1, seed=546)
+    big = bq.Context(0)
+    g = bq.Gauge(big, DIMS_A, U)
+    srv = bq.Server(big, 4, 4)
+    t32 = srv.submit(g, b32, 0.12, 1.5, inner_prec=1)
+    alone32 = _run_to_done(srv, [t32])[t32]
+    used_kept = big.hbm_used()  # gauge field, FP32-inner session and its kept operator
+    t64 = srv.submit(g, b64, 0.121, 1.5, inner_prec=0)
+    srv.step()
+    assert srv.pending() == (0, 1)
+    used_both = big.hbm_used()  # plus the FP64 session and its operator
+    alone64 = _run_to_done(srv, [t64])[t64]
+    srv.close()
+    assert used_both > used_kept
+    # a budget one byte short of holding both sessions with the FP32 operator still kept
+    ctx = bq.Context(0, hbm_budget=used_both - 1)
+    g2 = bq.Gauge(ctx, DIMS_A, U)
+    srv = bq.Server(ctx, 4, 4)
+    t32 = srv.submit(g2, b32, 0.12, 1.5, inner_prec=1)
+    r32 = _run_to_done(srv, [t32])[t32]
+    assert ctx.hbm_used() == used_kept
+    t64 = srv.submit(g2, b64, 0.121, 1.5, inner_prec=0)
+    r64 = _run_to_done(srv, [t64])[t64]
+    assert r32[0] == r64[0] == bq.BQ_OK
+    assert np.array_equal(r32[2], alone32[2]) and np.array_equal(r64[2], alone64[2])
+    assert ctx.hbm_used() < used_both
     srv.close()
 
 
@@ -243,3 +287,20 @@ def test_server_backfill_order(world):
         srv.close()
     assert first[0] == (2, 1)  # strict order: the narrow request waits behind the wide one
     assert first[8] == (1, 2)  # backfill: the narrow request runs beside the holder
+
+
+def test_server_idle_step_and_sessions_apart(world):
+    """A step with nothing queued or in flight returns at once; requests on two lattices, whose sessions
+    advance chunk by chunk independently, each give their result alone bit for bit."""
+    bq, ctx, G = world
+    srv = bq.Server(ctx, 4, 4)
+    assert srv.step() == [] and srv.pending() == (0, 0)
+    srv.close()
+    reqs = [(DIMS_B, G[DIMS_B][0], inputs.gaussian_spinor(DIMS_B, 3, seed=570), 0.123, 1),
+            (DIMS_A, G[DIMS_A][0], inputs.gaussian_spinor(DIMS_A, 1, seed=571), 0.119, 1),
+            (DIMS_A, G[DIMS_A][0], inputs.gaussian_spinor(DIMS_A, 2, seed=572), 0.121, 1)]
+    mix = serve(bq, ctx, reqs, slots=4, chunk=2)
+    for i, r in enumerate(reqs):
+        alone = serve(bq, ctx, [r], slots=4, chunk=2)[0]
+        assert mix[i][0] == alone[0] == bq.BQ_OK
+        assert np.array_equal(mix[i][2], alone[2]), i
