@@ -29,8 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # The serving leg runs one stream per server session: give them hardware queues of their own
-# (streams that share one run in submission order).  Set before the HIP runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# (streams that share one run in submission order).  Set before the HIP runtime starts; a
+# smaller value already in the environment is raised.
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "EO-clover Dslash GB/s (%HBM peak); mixed vs FP64 CG time-to-1e-10; p99 latency"
 HBM_PEAK_GBS = 8000.0

@@ -29,8 +29,9 @@ import numpy as np
 # number of hardware queues (4 unless set), and streams that share a queue run in submission
 # order: a small lattice's chunk would then wait behind a large lattice's kernels.  Four
 # sessions, the context stream and torch's stream need 8.  Effective only when set before the
-# HIP runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# HIP runtime starts; a smaller value already in the environment is raised.
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
