@@ -467,6 +467,8 @@ class Server:
         return t.value
 
     def step(self, max_done=4096):
+        """Tickets completed in one scheduling step; returns once a session's chunk has finished
+        (at once when nothing is in flight)."""
         done = (C.c_uint64 * max_done)()
         n = C.c_int()
         check(bq_server_step(self.h, done, max_done, C.byref(n)))
