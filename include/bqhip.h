@@ -425,8 +425,10 @@ int bq_server_step(bq_server s, uint64_t* done_tickets, int max_done, int* ndone
  * filled) and the ticket is forgotten. */
 int bq_server_result(bq_server s, uint64_t ticket, bq_solve_info* info);
 int bq_server_pending(bq_server s, int* queued, int* running);
-/* Free the sessions (workspaces, streams) the server holds for gauge field g, so that g can be
- * freed; BQ_ERR_BUSY while a request on g is queued or running. */
+/* Free the sessions (workspaces, streams, and the operators of retired requests that a session
+ * keeps for its next requests) the server holds for gauge field g, so that g can be freed;
+ * BQ_ERR_BUSY while a request on g is queued or running.  Kept operators are also freed when
+ * the context's HBM budget refuses a session or an operator. */
 int bq_server_release(bq_server s, bq_gauge g);
 /* Free the server, its sessions and its requests' operators (results not yet collected are lost). */
 int bq_server_free(bq_server s);
