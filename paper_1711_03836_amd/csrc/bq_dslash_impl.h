@@ -324,6 +324,33 @@ __device__ __forceinline__ void clover_mul(const cx<T> (&c)[18], const cx<T>* x,
         }
 }
 
+// clover_mul with the block read from the tile's LDS copy entry by entry as it is used (FP32 and
+// FP64 storage), instead of all 18 entries into registers first: the same products in the same
+// order, with 36 fewer values live
+template <class P>
+__device__ __forceinline__ void clover_mul_lds(const typename P::unit* S, int lane, int blk,
+                                               const cx<typename P::real>* x, cx<typename P::real>* y)
+{
+    static_assert(P::id != PREC_F16, "FP16 clover units hold two entries");
+    using T = typename P::real;
+    auto entry = [&](int k) {
+        const auto t = S[(blk * 18 + k) * kTile + lane];
+        return cx<T>{t.x, t.y};
+    };
+    const cx<T> d01 = entry(0), d23 = entry(1), d45 = entry(2);
+    const T d[6] = {d01.re, d01.im, d23.re, d23.im, d45.re, d45.im};
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] = cscale(d[i], x[i]);
+#pragma unroll
+    for (int i = 1; i < 6; i++)
+#pragma unroll
+        for (int jj = 0; jj < i; jj++) {
+            const cx<T> A = entry(3 + i * (i - 1) / 2 + jj);
+            y[i] = cmac(y[i], A, x[jj]);
+            y[jj] = cmacc(y[jj], A, x[i]);
+        }
+}
+
 // half of a spinor (block `blk`: complex 6*blk .. 6*blk+5) for FP32/FP64 storage
 template <class P>
 __device__ __forceinline__ void load_spinor_part(const SpinorPtr<P>& f, int col, int j, int blk,
@@ -515,15 +542,29 @@ __device__ __forceinline__ void hop_all(const Args<P, PR>& A, const Site& s, con
 // Epilogue of one tile for R columns: the linear combination and clover factor the caller
 // asked for (EPI), the store, and for EPI_TV / EPI_TVR the per-wave |.|^2 partials.  Lanes with
 // no active column pass nrm = 0 to the wave reduction.
-template <class P, class PR, int R, int EPI, bool PC, int LA>
+// SL: the workgroup staged the tile's (shared) clover in LDS at sclov
+template <class P, class PR, int R, int EPI, bool PC, int LA, bool SL = false>
 __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool (&act)[R], bool any, int c0,
                                          cx<typename P::real> (&acc)[R][12],
                                          const typename P::unit* sclov = nullptr)
 {
-    // the tile's clover from LDS when the workgroup staged it (shared clover only)
+    static_assert(!(SL && PC), "per-column clover is not staged");
+    // FP32 and FP64 read the staged clover entry by entry inside the multiply (cmul_blk); FP16
+    // units hold two entries and are unpacked whole
+    constexpr bool STREAM = SL && P::id != PREC_F16;
     auto clover_block = [&](const typename P::unit* C, int blk, cx<typename P::real>(&cb)[18]) {
-        if (!PC && sclov != nullptr) load_clover_block_lds<P>(sclov, j & (kTile - 1), blk, cb);
-        else load_clover_block<P, PC ? kBufNT : LA>(C, j, blk, cb);
+        if constexpr (STREAM) {
+            (void)C, (void)blk, (void)cb;
+        } else if constexpr (SL) {
+            load_clover_block_lds<P>(sclov, j & (kTile - 1), blk, cb);
+        } else {
+            load_clover_block<P, PC ? kBufNT : LA>(C, j, blk, cb);
+        }
+    };
+    auto cmul_blk = [&](const cx<typename P::real>(&cb)[18], int blk, const cx<typename P::real>* x,
+                        cx<typename P::real>* y) {
+        if constexpr (STREAM) clover_mul_lds<P>(sclov, j & (kTile - 1), blk, x, y);
+        else clover_mul(cb, x, y);
     };
     using T = typename P::real;
     using TR = typename PR::real;
@@ -560,7 +601,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
                     cx<T> x[6];
 #pragma unroll
                     for (int k = 0; k < 6; k++) x[k] = acc[r][blk * 6 + k];
-                    clover_mul(cb, x, &acc[r][blk * 6]);
+                    cmul_blk(cb, blk, x, &acc[r][blk * 6]);
                 }
                 phase_end(act, acc);
             }
@@ -581,21 +622,21 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
                 const T f = colf<PC>(A, c0 + r);
                 cx<T> x[6], y[6];
                 load_spinor_part(A.v, c0 + r, j, blk, x);
-                clover_mul(cb, x, y);
+                cmul_blk(cb, blk, x, y);
+                // |out|^2 in FP64 as the block is assembled (the terms in site order, as summed
+                // over the whole site)
 #pragma unroll
-                for (int k = 0; k < 6; k++) acc[r][blk * 6 + k] = caxpy(f, acc[r][blk * 6 + k], y[k]);
+                for (int k = 0; k < 6; k++) {
+                    acc[r][blk * 6 + k] = caxpy(f, acc[r][blk * 6 + k], y[k]);
+                    const cx<T> o = acc[r][blk * 6 + k];
+                    nrm[r] += (double)o.re * o.re + (double)o.im * o.im;
+                }
             }
             phase_end(act, acc);
         }
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            if (!act[r]) continue;
-            store_spinor(A.out, c0 + r, j, acc[r]);
-            double n = 0.0;
-#pragma unroll
-            for (int k = 0; k < 12; k++) n += (double)acc[r][k].re * acc[r][k].re + (double)acc[r][k].im * acc[r][k].im;
-            nrm[r] = n;
-        }
+        for (int r = 0; r < R; r++)
+            if (act[r]) store_spinor(A.out, c0 + r, j, acc[r]);
     } else {
         // w = C v + f*hop ; r_out = r_in - alpha*w, one clover block (half spinor) at a time
         static_assert(PR::id != PREC_F16, "the residual is kept in FP32 or FP64");
@@ -612,7 +653,7 @@ __device__ __forceinline__ void epilogue(const Args<P, PR>& A, int j, const bool
                 const TR al = A.alpha ? (TR)A.alpha[c] : TR(1);
                 cx<T> x[6], y[6];
                 load_spinor_part(A.v, c, j, blk, x);
-                clover_mul(cb, x, y);
+                cmul_blk(cb, blk, x, y);
                 cx<TR> rv[6];
                 load_spinor_part(A.rin, c, j, blk, rv);
                 typename PR::unit* rb = A.rout.d + c * A.rout.cstride;
@@ -979,9 +1020,17 @@ __device__ __forceinline__ void hh_step_lds(const Args<P, PR>& A, const Site& s,
 
 // FP64 holds twice the registers per column: its workgroups stop at 12 column waves (768 threads)
 template <class P> constexpr int lds_max_threads() { return P::id == PREC_F64 ? 768 : 1024; }
+// Waves per SIMD the compiler must leave room for.  A 12-wave workgroup puts 3 waves on each
+// SIMD, so two of them per CU need 6 (at most 80 VGPRs); left to itself the compiler gives the
+// FP32 K2 and K2-dagger stencils 90-96 VGPRs (FP16 storage 82), and then only one workgroup
+// fits a CU.  FP64 workgroups stop at 12 waves of 3 per SIMD with up to 168 VGPRs.
+template <class P, int R, bool XCHG> constexpr int lds_min_waves()
+{
+    return P::id != PREC_F64 && R == 1 && !XCHG ? 6 : 1;
+}
 
 template <class P, class PR, int R, int DAG, int EPI, int RECON, bool PC, int LA, bool XCHG>
-__global__ __launch_bounds__(lds_max_threads<P>()) void k_hop_lds(const Args<P, PR> A)
+__global__ __launch_bounds__(lds_max_threads<P>()) __attribute__((amdgpu_waves_per_eu(lds_min_waves<P, R, XCHG>(), 8))) void k_hop_lds(const Args<P, PR> A)
 {
     using T = typename P::real;
     using LC = typename LinkLds<P>::C;
@@ -1100,7 +1149,7 @@ __global__ __launch_bounds__(lds_max_threads<P>()) void k_hop_lds(const Args<P, 
         hh_step_lds<P, PR, R, DAG, RECON, NB, 6>(A, s, act, c0, lk, lane, d, acc);
         hh_step_lds<P, PR, R, DAG, RECON, NB, 7>(A, s, act, c0, lk, lane, d, acc);
     }
-    epilogue<P, PR, R, EPI, PC, LA>(A, j, act, any, c0, acc, CL ? sc : nullptr);
+    epilogue<P, PR, R, EPI, PC, LA, CL>(A, j, act, any, c0, acc, CL ? sc : nullptr);
 }
 
 template <class P>
