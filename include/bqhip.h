@@ -406,6 +406,12 @@ int bq_server_create(bq_context ctx, int slots, int chunk, bq_server* out);
  * steps in which the session has a chunk in flight do not count.  After that the session
  * admits nothing else until the waiting request fits.  0 = strict arrival order.  Default 8. */
 int bq_server_set_backfill(bq_server s, int steps);
+/* Sessions per (gauge field, mu, inner precision), 1..8 (default 1).  With more than one, a
+ * request goes to the fullest idle session of its key that has room for its columns, and a new
+ * session (its own workspace and stream) is opened when none has, up to this number: a wide
+ * request then starts beside a full session instead of waiting for its slots.  The admission
+ * order and backfill above hold per key.  Errors: BQ_ERR_INVALID. */
+int bq_server_set_sessions(bq_server s, int per_key);
 /* b: nrhs canonical spinors; x: an array of the same size that receives the solutions.
  * Each may be host or device memory (the runtime tells them apart by address; device
  * sources skip the PCIe transfers).  Both are owned by the caller and must stay valid

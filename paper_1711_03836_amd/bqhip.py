@@ -124,6 +124,7 @@ _sig = {
     "bq_autotune": (C.c_int, [_h, C.c_int, C.c_int]),
     "bq_server_create": (C.c_int, [_h, C.c_int, C.c_int, _P(_h)]),
     "bq_server_set_backfill": (C.c_int, [_h, C.c_int]),
+    "bq_server_set_sessions": (C.c_int, [_h, C.c_int]),
     "bq_server_release": (C.c_int, [_h, _h]),
     "bq_server_submit": (C.c_int, [_h, _h, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
                                    C.c_double, C.c_int, C.c_int, _P(C.c_uint64)]),
@@ -491,6 +492,10 @@ class Server:
 
     def set_backfill(self, steps):
         check(bq_server_set_backfill(self.h, int(steps)))
+
+    def set_sessions(self, per_key):
+        """Sessions per (gauge field, mu, inner precision); see bq_server_set_sessions."""
+        check(bq_server_set_sessions(self.h, int(per_key)))
 
     def release(self, gauge: Gauge):
         check(bq_server_release(self.h, gauge.h))

@@ -2899,6 +2899,7 @@ struct bq_server_s {
     bq_context ctx = nullptr;
     int cap = 16, chunk = 16;
     int backfill = 8;  // steps a blocked request may be passed by narrower ones of its session
+    int per_key = 1;   // sessions per (gauge field, mu, inner precision)
     std::vector<std::unique_ptr<Session>> sessions;
     std::vector<Request*> queue;  // FIFO
     std::map<uint64_t, std::unique_ptr<Request>> reqs;
@@ -2913,13 +2914,9 @@ static FieldArg col_arg(const Vec& v, int half, int col)
     return a;
 }
 
-static int session_get(bq_server S, bq_gauge g, double mu, int prec, Session** out)
+// a new, empty session of key (g, mu, prec)
+static int session_new(bq_server S, bq_gauge g, double mu, int prec, Session** out)
 {
-    for (auto& s : S->sessions)
-        if (s->g == g && s->mu == mu && s->prec == prec) {
-            *out = s.get();
-            return BQ_OK;
-        }
     auto s = std::make_unique<Session>();
     s->g = g;
     g->nsess++;  // released by the session's destructor
@@ -2945,6 +2942,32 @@ static int session_get(bq_server S, bq_gauge g, double mu, int prec, Session** o
     HIPCHK(hipMemcpy(s->w.cs.status, st.data(), sizeof(int) * s->cap, hipMemcpyHostToDevice));
     *out = s.get();
     S->sessions.push_back(std::move(s));
+    return BQ_OK;
+}
+
+// The session request q goes to: the fullest idle session of its key with room for its columns
+// (packing narrow requests leaves the key's other sessions free for wide ones), else a new
+// session while the key has fewer than S->per_key.  Otherwise *out = nullptr, *all_busy tells
+// whether every session of the key has a chunk in flight.  *first: the key's first session,
+// which stands for the key in the admission order (nullptr only if none exists yet).
+static int session_for(bq_server S, const Request* q, Session** out, Session** first, bool* all_busy)
+{
+    *out = *first = nullptr;
+    *all_busy = true;
+    int count = 0;
+    for (auto& sp : S->sessions) {
+        Session* s = sp.get();
+        if (s->g != q->g || s->mu != q->mu || s->prec != q->prec) continue;
+        if (!*first) *first = s;
+        count++;
+        if (s->busy) continue;
+        *all_busy = false;
+        if (s->cap - s->used >= q->nrhs && (!*out || s->used > (*out)->used)) *out = s;
+    }
+    if (*out || count >= S->per_key) return BQ_OK;
+    CHK(session_new(S, q->g, q->mu, q->prec, out));
+    if (!*first) *first = *out;
+    *all_busy = false;
     return BQ_OK;
 }
 
@@ -3249,28 +3272,32 @@ static int admit_queued(bq_server S, std::set<Request*>& blocked, const std::fun
 {
     std::vector<Session*> fresh;
     std::vector<Request*> keep;
-    std::map<Session*, Request*> head;  // first blocked request per session
+    std::map<Session*, Request*> head;  // first blocked request per key (its first session)
     for (Request* q : S->queue) {
-        Session* s = nullptr;
-        int rc = session_get(S, q->g, q->mu, q->prec, &s);
-        if (rc == BQ_ERR_OOM && trim_spares(S)) rc = session_get(S, q->g, q->mu, q->prec, &s);
-        if (rc == BQ_ERR_OOM) {
-            keep.push_back(q);
-            continue;
+        Session *s = nullptr, *first = nullptr;
+        bool all_busy = true;
+        int rc = session_for(S, q, &s, &first, &all_busy);
+        if (rc == BQ_ERR_OOM && trim_spares(S)) rc = session_for(S, q, &s, &first, &all_busy);
+        if (rc == BQ_ERR_OOM) {  // no memory for a new session: wait for an existing one, if any
+            rc = BQ_OK;
+            s = nullptr;
+            if (!first) {
+                keep.push_back(q);
+                continue;
+            }
         }
         if (rc != BQ_OK) {
             finish_failed(q, rc);
             report(q);
             continue;
         }
-        if (s->busy) {
+        if (!s && all_busy) {  // every session of the key has a chunk in flight: no step is waited
             keep.push_back(q);
             continue;
         }
-        Request*& h = head[s];
-        const bool fits = s->cap - s->used >= q->nrhs;
+        Request*& h = head[first];
         const bool may_pass = h == nullptr || h->waited < S->backfill;
-        if (!fits || !may_pass) {
+        if (!s || !may_pass) {
             if (h == nullptr) h = q;
             keep.push_back(q);
             continue;
@@ -3378,6 +3405,13 @@ int bq_server_set_backfill(bq_server S, int steps)
 {
     if (!S || steps < 0) return fail(BQ_ERR_INVALID, "NULL server or negative step count");
     S->backfill = steps;
+    return BQ_OK;
+}
+
+int bq_server_set_sessions(bq_server S, int per_key)
+{
+    if (!S || per_key < 1 || per_key > 8) return fail(BQ_ERR_INVALID, "NULL server or sessions per key outside 1..8");
+    S->per_key = per_key;
     return BQ_OK;
 }
 

@@ -141,6 +141,7 @@ def main():
     ap.add_argument("--qps", type=float, default=None)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--sessions", type=int, default=1, help="server sessions per gauge field (bq_server_set_sessions)")
     ap.add_argument("--inner", choices=["f64", "f32", "f16"], default="f32")
     ap.add_argument("--seed", type=int, default=2017)
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
@@ -153,10 +154,11 @@ def main():
     world = World(bq, ctx)
     out = {"workload": "serving mix: lattices {8^4, 16^3x32, 24^3x48, 32^3x64}, kappa U[0.118,0.124], c_SW 1.5, "
                        "1-12 Gaussian RHS, tol 1e-10, U=exp(0.2 i H)", "slots": args.slots, "chunk": args.chunk,
-           "inner_prec": args.inner, "runs": []}
+           "sessions": args.sessions, "inner_prec": args.inner, "runs": []}
     sat = None
     if args.qps is None:
         server = bq.Server(ctx, args.slots, args.chunk)
+        server.set_sessions(args.sessions)
         r = run(bq, world, server, make_requests(args.saturation_requests, args.seed + 1), None, inner_prec=prec,
                 outstanding=args.saturation_outstanding)
         server.close()
@@ -166,6 +168,7 @@ def main():
     rates = [args.qps] if args.qps else [f * sat for f in args.load]
     for q in rates:
         server = bq.Server(ctx, args.slots, args.chunk)
+        server.set_sessions(args.sessions)
         r = run(bq, world, server, make_requests(args.requests, args.seed), q, seed=args.seed, inner_prec=prec)
         server.close()
         r["load"] = q / sat if sat else None

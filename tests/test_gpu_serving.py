@@ -304,3 +304,25 @@ def test_server_idle_step_and_sessions_apart(world):
         alone = serve(bq, ctx, [r], slots=4, chunk=2)[0]
         assert mix[i][0] == alone[0] == bq.BQ_OK
         assert np.array_equal(mix[i][2], alone[2]), i
+
+
+def test_server_sessions_per_key(world):
+    """With two sessions per gauge field, a request that does not fit the first session's free slots
+    opens a second one and starts at once; every result is bitwise its result alone."""
+    bq, ctx, G = world
+    g = G[DIMS_A][0]
+    bs = [inputs.gaussian_spinor(DIMS_A, 3, seed=580 + i) for i in range(3)]
+    alone = [serve(bq, ctx, [(DIMS_A, g, b, 0.12 + 0.001 * i, 1)], slots=4, chunk=4)[0] for i, b in enumerate(bs)]
+    for per_key, running in ((1, 1), (2, 2)):
+        srv = bq.Server(ctx, 4, 4)
+        srv.set_sessions(per_key)
+        tickets = [srv.submit(g, b, 0.12 + 0.001 * i, 1.5) for i, b in enumerate(bs)]
+        srv.step()
+        assert srv.pending() == (len(bs) - running, running), per_key
+        res = _run_to_done(srv, tickets)
+        srv.close()
+        for i, t in enumerate(tickets):
+            assert res[t][0] == bq.BQ_OK
+            assert np.array_equal(res[t][2], alone[i][2]), (per_key, i)
+    with pytest.raises(bq.BqError):
+        bq.Server(ctx, 4, 4).set_sessions(0)
