@@ -385,8 +385,9 @@ int bq_autotune(bq_op op, int prec, int nrhs);
  * The paper has no serving layer; the server batches solves of the cg solver (section
  * "Algorithms") from many callers.
  * Requests M x = b (the BQ_SYS_M system) on resident gauge fields are queued by
- * bq_server_submit and advanced by bq_server_step.  Requests run in sessions (one
- * per gauge field, mu and inner precision, `slots` columns each) that advance
+ * bq_server_submit and advanced by bq_server_step.  Requests run in sessions (by
+ * default one per gauge field, mu and inner precision, see bq_server_set_sessions;
+ * `slots` columns each) that advance
  * independently, one chunk of CG iterations at a time, on streams of their own:
  * a step retires the requests whose columns have converged in the sessions whose
  * chunk has finished, admits queued requests into free column slots of those
